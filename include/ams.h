@@ -1,0 +1,222 @@
+/*
+ * ams.h -- C ABI of the MI355X (gfx950) adaptive multi-level sample sort.
+ *
+ * Problem (Section 1, problem statement): permute n elements so that they are
+ * sorted.  Equal keys keep their input order: the paper makes all keys unique
+ * by breaking ties with the input position (Section 2 and Appendix D), which
+ * on one array is the same as a stable sort.  The result is therefore unique:
+ * output position i holds the element whose (ord(key), input position) pair is
+ * the i-th smallest, keys are returned bit for bit and the payload follows its
+ * key.  ord is the identity for unsigned integers and IEEE 754-2008 totalOrder
+ * on the bit pattern for float32 (-NaN < -inf < ... < -0 < +0 < ... < +NaN);
+ * no floating-point arithmetic is done on keys.
+ *
+ * Method (Section 6, AMS-sort): per level, a random sample of a*b*r keys is
+ * sorted by all-pairs ranking (Section 4.2), b*r-1 splitters of equidistant
+ * rank are taken from it, every key is classified into one of b*r buckets
+ * (plus equality buckets for keys equal to a splitter, Appendix D), bucket
+ * sizes are summed, the buckets are packed into at most r groups of minimal
+ * maximum load (Section 6 and its lemma; Appendix C), and the keys are
+ * scattered stably into their groups, which are the next level's
+ * subproblems.  Groups small enough for one workgroup's LDS are finished by
+ * an in-LDS split followed by all-pairs ranking (Section 4.2).
+ *
+ * Memory.  Every key/payload pointer is DEVICE memory owned by the caller;
+ * the library never frees caller memory.  `stream` is a hipStream_t (NULL =
+ * the default stream).  All sort calls only enqueue work on `stream` and
+ * return; results are ready when the stream reaches that point.  A kernel
+ * fault surfaces at the caller's next synchronisation.
+ *
+ * Errors.  Functions return 0 (AMS_OK) or a negative ams_status; no C++
+ * exception crosses this boundary.  ams_last_error() gives a message for the
+ * calling thread's last failure.  n = 0 and n = 1 are valid no-op-like sorts
+ * (n = 1 still copies d_in to d_out).
+ */
+#ifndef AMS_H
+#define AMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMS_U32 = 1, /* uint32_t keys */
+  AMS_U64 = 2, /* uint64_t keys (the paper's 64-bit integers, Section 7) */
+  AMS_F32 = 3  /* float32 keys, ordered by totalOrder on their bits */
+} ams_key_t;
+
+typedef int ams_status;
+#define AMS_OK 0
+#define AMS_EINVAL (-1)       /* bad argument: NULL pointer with n > 0, unknown key type, ... */
+#define AMS_ENOMEM (-2)       /* workspace too small / allocation failed / request can never fit */
+#define AMS_EHIP (-3)         /* a HIP runtime call failed */
+#define AMS_EAGAIN (-4)       /* server: pending queue full, try again */
+#define AMS_EUNSUPPORTED (-5) /* size or option outside what this build supports */
+#define AMS_ENOTFOUND (-6)    /* server: unknown or released ticket */
+
+/* Tuning parameters.  A zero field means "choose automatically" (the built-in
+ * autotuned defaults); passing NULL means all defaults.  Names follow the
+ * paper: k is the number of groups per level (the paper's r), b the
+ * overpartitioning factor, a the oversampling factor (Section 6). */
+typedef struct {
+  uint32_t levels;             /* partition levels before the base case */
+  uint32_t k;                  /* groups per level r; power of two, 2..1024 */
+  uint32_t overpartition_b;    /* buckets per group b; power of two, k*b <= 2048 */
+  uint32_t samples_per_bucket; /* oversampling factor a */
+  uint32_t tile_keys;          /* keys per workgroup tile in a level pass (multiple of 4096) */
+  uint32_t base_cutoff;        /* largest bucket handed to the all-pairs ranker, <= 1024 */
+  uint64_t seed;               /* sampling seed (0 = fixed default) */
+  uint32_t flags;              /* AMS_FLAG_* */
+  uint32_t leaf_capacity;      /* test hook: subproblems larger than this are not finished in
+                                  LDS (0 = the workgroup's capacity); lowering it forces the
+                                  slow paths on small inputs */
+} ams_params;
+
+#define AMS_FLAG_EQ_ALWAYS 1u /* equality buckets on for every subproblem */
+
+/* Bytes of device workspace a call with these arguments needs.  Returns 0 on
+ * invalid arguments.  ams_sort_* accept d_ws = NULL, in which case they
+ * allocate (stream-ordered) and free the workspace themselves. */
+size_t ams_workspace_bytes(ams_key_t t, size_t n, int with_vals, const ams_params *p);
+
+/* Workspace for ams_sort_batch; h_offsets is the host copy of the num+1
+ * segment offsets. */
+size_t ams_batch_workspace_bytes(ams_key_t t, const uint64_t *h_offsets, size_t num,
+                                 int with_vals, const ams_params *p);
+
+/* Sort n keys.  d_in (n keys) and d_out (n keys) may be the same buffer
+ * (in-place).  n must be below 2^32.  Section 6 (AMS-sort), Section 1
+ * (output requirement). */
+ams_status ams_sort_keys(ams_key_t t, const void *d_in, void *d_out, size_t n, void *d_ws,
+                         size_t ws_bytes, void *stream, const ams_params *p);
+
+/* Stable key/payload sort: payload d_vin[i] follows key d_kin[i].  Output
+ * arrays may alias the inputs.  Section 6; stability from the position
+ * tie-break of Section 2 / Appendix D. */
+ams_status ams_sort_pairs(ams_key_t t, const void *d_kin, const uint32_t *d_vin, void *d_kout,
+                          uint32_t *d_vout, size_t n, void *d_ws, size_t ws_bytes, void *stream,
+                          const ams_params *p);
+
+/* Batched sort: segment i = elements [h_offsets[i], h_offsets[i+1]) of the
+ * key (and optional payload) arrays is sorted independently, each result
+ * identical to sorting that segment alone.  h_offsets (host, num+1 entries,
+ * non-decreasing, h_offsets[0] = 0) plans the work; d_offsets (device copy,
+ * may be NULL) saves the upload.  d_vin/d_vout are NULL for keys-only.  All
+ * segments run through the same level kernels together; no per-segment
+ * launches.  Section 6 applied to many independent inputs. */
+ams_status ams_sort_batch(ams_key_t t, const void *d_kin, const uint32_t *d_vin, void *d_kout,
+                          uint32_t *d_vout, const uint64_t *h_offsets, const uint64_t *d_offsets,
+                          size_t num, void *d_ws, size_t ws_bytes, void *stream,
+                          const ams_params *p);
+
+/* Message for the calling thread's most recent error ("" if none). */
+const char *ams_last_error(void);
+
+/* Library version string. */
+const char *ams_version(void);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent sort requests.
+ *
+ * A server owns worker streams on one device and a budget of device memory.
+ * ams_submit queues a request whose keys (and optional payload) already sit
+ * in device memory; requests are admitted while the bytes they need (result
+ * buffers + workspace) fit in the budget, admitted requests are batched as
+ * they arrive and sorted by ams_sort_batch-equivalent launches on the worker
+ * streams, so batches overlap on the device.  Results stay on the device in
+ * server-owned buffers until released.  Each result equals sorting that
+ * request alone.
+ * ------------------------------------------------------------------------ */
+typedef struct ams_server ams_server;
+
+typedef struct {
+  uint64_t n;          /* keys in the request */
+  int32_t key_type;    /* ams_key_t */
+  int32_t status;      /* AMS_OK, or the error that ended the request */
+  uint64_t batch_id;   /* batch the request ran in */
+  uint32_t batch_size; /* requests in that batch */
+  uint32_t reserved;
+  double t_submit_us;  /* host clock (microseconds since server creation) */
+  double t_admit_us;   /* admitted against the memory budget */
+  double t_launch_us;  /* batch enqueued */
+  double t_done_us;    /* completion observed */
+  double gpu_ms;       /* device time of the batch (event pair) */
+} ams_req_stats;
+
+/* Create a server on `device` with `hbm_budget` bytes (0 = 80% of free
+ * memory), at most `max_pending` queued + running requests (0 = 4096) and
+ * `n_streams` worker streams (0 = 2).  Returns NULL and sets *st on failure. */
+ams_server *ams_server_create(int device, size_t hbm_budget, uint32_t max_pending,
+                              uint32_t n_streams, ams_status *st);
+
+/* Queue a request.  d_keys must stay valid until the request completes.
+ * Returns AMS_ENOMEM if the request alone can never fit the budget and
+ * AMS_EAGAIN if max_pending requests are already queued or running. */
+ams_status ams_submit(ams_server *srv, ams_key_t t, const void *d_keys, const uint32_t *d_vals,
+                      size_t n, uint64_t *ticket);
+
+/* Non-blocking completion check; *done = 1 when finished (stats filled). */
+ams_status ams_poll(ams_server *srv, uint64_t ticket, int *done, ams_req_stats *stats);
+
+/* Block until the request is finished. */
+ams_status ams_wait(ams_server *srv, uint64_t ticket, ams_req_stats *stats);
+
+/* Device pointers of a finished request's sorted keys / payload (NULL when
+ * the request had none).  Valid until ams_release. */
+ams_status ams_result(ams_server *srv, uint64_t ticket, void **d_keys, uint32_t **d_vals);
+
+/* Free a finished request's result buffers and forget the ticket. */
+ams_status ams_release(ams_server *srv, uint64_t ticket);
+
+/* Drain outstanding work, free everything. */
+void ams_server_destroy(ams_server *srv);
+
+/* ------------------------------------------------------------------------
+ * Step entry points: one step of the path on one subproblem, for checking
+ * each kernel against its plain definition.  Keys here are ord values
+ * (uint32 for AMS_U32/AMS_F32, uint64 for AMS_U64) unless stated.
+ * ------------------------------------------------------------------------ */
+
+/* Sample and splitters (Section 6; sample sorted by all-pairs rank, Section
+ * 4.2).  Draws a*m positions of d_keys[0..n) with SplitMix64 keyed by (seed,
+ * level 0, root 0, offset 0), ranks the sample, and writes the m-1 splitters
+ * of rank j*a-1 (j = 1..m-1) as ord values to d_splitters.  m is a power of
+ * two in 2..2048 and a*m <= 8192 (uint64) or 16384 (32-bit keys). */
+ams_status ams_step_splitters(ams_key_t t, const void *d_keys, size_t n, uint32_t m, uint32_t a,
+                              uint64_t seed, void *d_splitters, void *stream);
+
+/* One level pass with given sorted splitters (ord values, m-1 of them):
+ * classification (with equality buckets when two splitters are equal or
+ * flags has AMS_FLAG_EQ_ALWAYS), bucket histogram (d_hist, 2m-1 uint32
+ * entries; only the first m are written without equality buckets), bucket
+ * grouping into at most r groups, children (d_children: 4 uint32 per child
+ * = first id, end id, size, kind 0 regular / 1 final; *n_children set on the
+ * host after the call synchronises `stream`), and the stable scatter of
+ * d_in[0..n) into d_out (raw keys in, ord-ordered children out, keys
+ * bit-identical).  Sections 6 and 4.3; Appendix C and D. */
+ams_status ams_step_level(ams_key_t t, const void *d_in, void *d_out, size_t n,
+                          const void *d_splitters, uint32_t m, uint32_t r, uint32_t flags,
+                          uint32_t *d_hist, uint32_t *d_children, uint32_t *n_children,
+                          void *stream);
+
+/* Bucket grouping alone (Section 6 and its lemma; Appendix C): w[0..nb)
+ * weights -> d_out[0] = optimal maximum load L*, d_out[1] = number of groups
+ * g, d_out[2..2+g) = start index of each greedy group under L*.  nb <= 4095. */
+ams_status ams_step_pack(const uint32_t *d_w, uint32_t nb, uint32_t r, uint32_t *d_out,
+                         void *stream);
+
+/* Base case alone: sort one array of n <= 8192 keys (and optional payload)
+ * inside one workgroup by an in-LDS split followed by all-pairs ranking
+ * (Section 4.2).  base_cutoff as in ams_params (0 = default). */
+ams_status ams_step_base_case(ams_key_t t, const void *d_kin, const uint32_t *d_vin,
+                              void *d_kout, uint32_t *d_vout, size_t n, uint32_t base_cutoff,
+                              void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMS_H */
