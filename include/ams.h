@@ -168,6 +168,11 @@ ams_status ams_wait(ams_server *srv, uint64_t ticket, ams_req_stats *stats);
  * the request had none).  Valid until ams_release. */
 ams_status ams_result(ams_server *srv, uint64_t ticket, void **d_keys, uint32_t **d_vals);
 
+/* Copy a finished request's sorted keys / payload into caller device buffers
+ * (either may be NULL), enqueued on `stream`. */
+ams_status ams_result_copy(ams_server *srv, uint64_t ticket, void *d_keys, uint32_t *d_vals,
+                           void *stream);
+
 /* Free a finished request's result buffers and forget the ticket. */
 ams_status ams_release(ams_server *srv, uint64_t ticket);
 

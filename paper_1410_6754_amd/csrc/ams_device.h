@@ -1,0 +1,250 @@
+// Device-side building blocks of the sample sort: key encodings, the
+// SplitMix64 sampling stream, wavefront primitives and the splitter-tree
+// descent.  gfx950 only (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define AMS_DEV __device__ __forceinline__
+#define AMS_HD __host__ __device__ __forceinline__
+
+namespace ams {
+
+enum : int { KT_U32 = 1, KT_U64 = 2, KT_F32 = 3 };
+
+// Where a subproblem's elements currently live.
+enum : uint32_t { BUF_IN = 0, BUF_TMP = 1, BUF_OUT = 2 };
+// Leaf kinds for the base-case kernel.
+enum : uint32_t { LEAF_REG = 0, LEAF_COPY = 1, LEAF_BIG = 2 };
+// Child kinds (bucket grouping output).
+enum : uint32_t { CHILD_REG = 0, CHILD_FINAL = 1 };
+
+constexpr uint32_t WAVE = 64;
+constexpr uint64_t GOLDEN_GAMMA = 0x9E3779B97F4A7C15ull;
+
+// ---------------------------------------------------------------------------
+// Keys.  T is the stored word; enc maps raw bits to an unsigned value whose
+// integer order is the key order (identity for integers, IEEE totalOrder for
+// float32: set the sign bit of non-negative values, invert negative ones).
+// ---------------------------------------------------------------------------
+template <int KT> struct Key;
+template <> struct Key<KT_U32> {
+  typedef uint32_t T;
+  static AMS_DEV T enc(T x) { return x; }
+  static AMS_DEV T dec(T x) { return x; }
+};
+template <> struct Key<KT_U64> {
+  typedef uint64_t T;
+  static AMS_DEV T enc(T x) { return x; }
+  static AMS_DEV T dec(T x) { return x; }
+};
+template <> struct Key<KT_F32> {
+  typedef uint32_t T;
+  static AMS_DEV T enc(T x) { return (x & 0x80000000u) ? ~x : (x | 0x80000000u); }
+  static AMS_DEV T dec(T x) { return (x & 0x80000000u) ? (x & 0x7FFFFFFFu) : ~x; }
+};
+
+// ---------------------------------------------------------------------------
+// Subproblems.  A root is one independent input; a segment is a contiguous
+// range of a root in one of its three buffers.
+// ---------------------------------------------------------------------------
+struct Root {
+  const void *kin;
+  const uint32_t *vin;
+  void *kout;
+  uint32_t *vout;
+  uint64_t n;
+  uint64_t tmp_off;  // element offset of this root inside the TMP buffers
+};
+
+struct Seg {
+  uint32_t off;   // element offset inside the root
+  uint32_t size;  // elements
+  uint32_t root;
+  uint32_t meta;  // buf | kind << 4 | dst << 8
+};
+
+AMS_HD uint32_t seg_meta(uint32_t buf, uint32_t kind, uint32_t dst) {
+  return buf | (kind << 4) | (dst << 8);
+}
+AMS_DEV uint32_t seg_buf(uint32_t meta) { return meta & 15u; }
+AMS_DEV uint32_t seg_kind(uint32_t meta) { return (meta >> 4) & 15u; }
+AMS_DEV uint32_t seg_dst(uint32_t meta) { return (meta >> 8) & 15u; }
+
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea, Flood 2014): output i of a generator at state s is
+// mix64(s + i * gamma).  Sample positions are floor(n * u / 2^64).
+// ---------------------------------------------------------------------------
+AMS_DEV uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+AMS_DEV uint64_t stream_state(uint64_t seed, uint32_t level, uint32_t root, uint64_t off) {
+  uint64_t s = mix64(seed + GOLDEN_GAMMA);
+  s = mix64(s ^ (uint64_t)(level + 1));
+  s = mix64(s ^ (uint64_t)root);
+  return mix64(s ^ off);
+}
+
+AMS_DEV uint32_t draw_pos(uint64_t state, uint32_t i, uint32_t n) {
+  uint64_t u = mix64(state + (uint64_t)(i + 1) * GOLDEN_GAMMA);
+  return (uint32_t)__umul64hi(u, (uint64_t)n);
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront primitives (wave64).
+// ---------------------------------------------------------------------------
+AMS_DEV uint32_t lane_id() { return __lane_id(); }
+AMS_DEV uint64_t ballot(bool p) { return __ballot(p ? 1 : 0); }
+// number of set bits of mask below this lane
+AMS_DEV uint32_t bits_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Lanes (among `valid`) that hold the same value c, found with one ballot per
+// bit of c (nbits bits are compared).
+AMS_DEV uint64_t match_lanes(uint32_t c, bool valid, uint32_t nbits) {
+  uint64_t m = ballot(valid);
+  for (uint32_t b = 0; b < nbits; ++b) {
+    bool bit = (c >> b) & 1u;
+    uint64_t bm = ballot(bit);
+    m &= bit ? bm : ~bm;
+  }
+  return m;
+}
+
+template <typename T> AMS_DEV T wave_sum(T v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+template <typename T> AMS_DEV T wave_max(T v) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    T o = __shfl_xor(v, d, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+template <typename T> AMS_DEV T wave_min(T v) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    T o = __shfl_xor(v, d, 64);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Splitter tree.  tree[1..m-1] holds the m-1 sorted splitters in Eytzinger
+// (breadth-first) order; descending with "x > node -> right child" for log2 m
+// steps ends at m + #{splitters < x}.  The splitter of sorted index j-1
+// (j = 1..m-1, in-order rank j) sits at node (m + j) >> (ctz(j) + 1).
+// ---------------------------------------------------------------------------
+AMS_DEV uint32_t eytzinger_slot(uint32_t j, uint32_t m) { return (m + j) >> (__builtin_ctz(j) + 1); }
+
+template <typename K> AMS_DEV uint32_t tree_descend(K x, const K *tree, uint32_t logm) {
+  uint32_t i = 1;
+  for (uint32_t l = 0; l < logm; ++l) i = 2 * i + (x > tree[i] ? 1u : 0u);
+  return i - (1u << logm);
+}
+
+// Bucket id: b = #{splitters < x}; with equality buckets, keys equal to the
+// splitter just above (sorted spl[b], b < m-1) get id 2b+1, others 2b.
+template <typename K>
+AMS_DEV uint32_t classify_id(K x, const K *tree, const K *spl, uint32_t logm, bool eq) {
+  uint32_t b = tree_descend(x, tree, logm);
+  if (!eq) return b;
+  uint32_t m = 1u << logm;
+  bool has_upper = b < m - 1;
+  K up = spl[has_upper ? b : 0];
+  return 2 * b + ((has_upper && x == up) ? 1u : 0u);
+}
+
+// Number of elements < x (strict) or <= x in a sorted array of n = 2^k.
+template <typename K> AMS_DEV uint32_t count_less(const K *a, uint32_t n, K x) {
+  uint32_t base = 0;
+  while (n > 1) {
+    uint32_t half = n >> 1;
+    base = (a[base + half - 1] < x) ? base + half : base;
+    n -= half;
+  }
+  return base + (a[base] < x ? 1u : 0u);
+}
+template <typename K> AMS_DEV uint32_t count_less_eq(const K *a, uint32_t n, K x) {
+  uint32_t base = 0;
+  while (n > 1) {
+    uint32_t half = n >> 1;
+    base = (a[base + half - 1] <= x) ? base + half : base;
+    n -= half;
+  }
+  return base + (a[base] <= x ? 1u : 0u);
+}
+
+// ---------------------------------------------------------------------------
+// Item distribution for persistent grids.  Workgroups are dispatched
+// round-robin over the 8 XCDs, so block b runs on XCD b % 8; each XCD gets a
+// contiguous range of items so that neighbouring tiles share one L2.
+// ---------------------------------------------------------------------------
+struct ItemRange {
+  uint32_t first, step, end;
+};
+AMS_DEV ItemRange xcd_items(uint32_t total) {
+  uint32_t G = gridDim.x, b = blockIdx.x;
+  ItemRange r;
+  if ((G & 7u) != 0 || total < G) {
+    r.first = b;
+    r.step = G;
+    r.end = total;
+    return r;
+  }
+  uint32_t x = b & 7u, j = b >> 3, G8 = G >> 3;
+  uint32_t chunk = (total + 7u) >> 3;
+  uint32_t lo = x * chunk;
+  uint32_t hi = lo + chunk < total ? lo + chunk : total;
+  r.first = lo + j;
+  r.step = G8;
+  r.end = hi;
+  return r;
+}
+
+// Largest i in [0, n) with prefix[i] <= g (prefix non-decreasing, prefix[0] = 0).
+AMS_DEV uint32_t find_owner(const uint32_t *prefix, uint32_t n, uint32_t g) {
+  uint32_t lo = 0, hi = n;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (prefix[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// In-place exclusive scan of a[0..n) by a block of NT threads; tmp holds NT
+// words of LDS.  Returns the total.  Ends with a barrier.
+template <int NT> AMS_DEV uint32_t block_exscan(uint32_t *a, uint32_t n, uint32_t *tmp) {
+  const uint32_t tid = threadIdx.x;
+  uint32_t per = (n + NT - 1) / NT;
+  uint32_t lo = tid * per < n ? tid * per : n;
+  uint32_t hi = lo + per < n ? lo + per : n;
+  uint32_t s = 0;
+  for (uint32_t i = lo; i < hi; ++i) s += a[i];
+  tmp[tid] = s;
+  __syncthreads();
+  for (uint32_t d = 1; d < (uint32_t)NT; d <<= 1) {
+    uint32_t v = tid >= d ? tmp[tid - d] : 0u;
+    __syncthreads();
+    tmp[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = tid ? tmp[tid - 1] : 0u;
+  uint32_t total = tmp[NT - 1];
+  for (uint32_t i = lo; i < hi; ++i) {
+    uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  __syncthreads();
+  return total;
+}
+
+}  // namespace ams

@@ -1,0 +1,1546 @@
+// Adaptive multi-level sample sort (Section 6) on gfx950: level kernels, the
+// base-case kernel, planning and launch.
+//
+// One level runs over every active subproblem at once:
+//   k_plan           tile / sample-block prefix sums over the active list
+//   k_sample_blocks  random sample (with replacement), blocks of 256 ranked by
+//                    comparing all pairs (Section 4.2)
+//   k_sample_rank    rank across the sorted blocks by binary search (the merge
+//                    step of Section 4.2); the elements of rank j*a-1 become the
+//                    splitters, stored sorted and as an Eytzinger tree
+//   k_count          classify every key against the tree held in LDS (with the
+//                    equality buckets of Appendix D when splitters repeat) and
+//                    count per tile with per-wavefront LDS histograms
+//   k_block_reduce   histograms summed over blocks of tiles
+//   k_pack           bucket totals; optimal grouping of buckets into at most r
+//                    groups (Section 6 and its lemma; Appendix C search);
+//                    children in key order; per-block child offsets
+//   k_tile_scan      per-tile start offset of every child (child-major,
+//                    tile-minor exclusive scan: Section 4.3 prefix sums)
+//   k_scatter        stable scatter of every key into its child through LDS
+// and the leaves are finished by k_finish: in-LDS split with a small sampled
+// splitter set, then all-pairs ranking inside every small bucket.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "ams_engine.h"
+
+namespace ams {
+
+// ---------------------------------------------------------------------------
+// device state
+// ---------------------------------------------------------------------------
+struct Ctr {
+  uint32_t nact[MAXLEV + 1];
+  uint32_t nleaf;
+  uint32_t P, ntile, nblk, nsblk;
+  uint32_t overflow;
+  uint32_t pad[5];
+};
+
+struct Ws {
+  Root *roots;
+  uint32_t nroots;
+  void *tmpK;
+  uint32_t *tmpV;
+  Ctr *ctr;
+  Seg *act[MAXLEV + 1];
+  uint32_t capAct[MAXLEV + 1];
+  Seg *leaves;
+  uint32_t capLeaf;
+  uint32_t *tileStart, *blkStart, *sampStart;
+  void *samp, *spl, *tree;
+  uint8_t *eqOn;
+  uint32_t *hist, *blkHist, *blkOff, *tileOff;
+  uint16_t *i2c, *cfirst;
+  uint32_t *cstart;
+  uint8_t *cdst;
+  uint32_t *nch;
+  uint32_t capTile, capBlk, capSBlk;
+  uint32_t *dbgHist, *dbgChildren, *dbgNChild;
+};
+
+struct Lev {
+  uint32_t level, L, last, shrink;
+  uint32_t rmax, b, a, mmax, Smax, TC, TB, HS, CH, rankG;
+  uint32_t C, flags, Scap;
+  uint64_t seed;
+};
+
+struct LevTable {
+  Lev l[MAXLEV];
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+AMS_HD uint32_t ilog2c(uint32_t x) {  // ceil(log2 x), x >= 1
+  uint32_t l = 0;
+  while ((1u << l) < x) ++l;
+  return l;
+}
+
+// Shape of one subproblem of N keys: r groups (the paper's r), m = b*r buckets
+// and a sample of S = a*m keys (whole blocks of 256, at most Scap).  With
+// `shrink`, the number of groups is cut to what the base case needs (about
+// C/2 keys per group), so small subproblems are not over-partitioned.
+AMS_HD void seg_shape(uint32_t N, uint32_t C, bool shrink, uint32_t rmax,
+                                       uint32_t b, uint32_t a, uint32_t Scap, uint32_t &logr,
+                                       uint32_t &logm, uint32_t &S) {
+  uint32_t r = rmax;
+  if (shrink) {
+    uint64_t need = (2ull * N + C - 1) / C;
+    r = 2;
+    while (r < need && r < rmax) r <<= 1;
+    if (r > rmax) r = rmax;
+  }
+  uint32_t m = r * b;
+  if (m > 2048) m = 2048;
+  if (m < 2) m = 2;
+  logr = ilog2c(r);
+  logm = ilog2c(m);
+  uint64_t s = (uint64_t)a * m;
+  s = (s + 255) & ~255ull;
+  if (s > Scap) s = Scap;
+  S = (uint32_t)s;
+}
+
+AMS_DEV uint32_t meta_logm(uint32_t meta) { return (meta >> 12) & 15u; }
+AMS_DEV uint32_t meta_logr(uint32_t meta) { return (meta >> 16) & 15u; }
+AMS_HD uint32_t make_meta(uint32_t buf, uint32_t kind, uint32_t dst,
+                                          uint32_t logm, uint32_t logr) {
+  return buf | (kind << 4) | (dst << 8) | (logm << 12) | (logr << 16);
+}
+
+// Buffer the children of a subproblem go to.  Read from the caller's input,
+// the first level writes the output buffer when an odd number of levels
+// remain (so the last level lands in the output) and input and output do not
+// alias; later levels alternate between TMP and OUT.
+AMS_HD uint32_t dst_for(uint32_t buf, bool inplace, uint32_t L, uint32_t lv) {
+  if (buf == BUF_IN) return (((L - lv) & 1u) && !inplace) ? BUF_OUT : BUF_TMP;
+  return buf == BUF_TMP ? BUF_OUT : BUF_TMP;
+}
+
+AMS_DEV bool root_inplace(const Root &R) {
+  return R.kin == (const void *)R.kout || (R.vin != nullptr && R.vin == R.vout);
+}
+
+template <typename K> AMS_DEV K *kptr(const Ws &w, const Root &R, uint32_t buf) {
+  if (buf == BUF_IN) return (K *)R.kin;
+  if (buf == BUF_OUT) return (K *)R.kout;
+  return (K *)w.tmpK + R.tmp_off;
+}
+AMS_DEV uint32_t *vptr(const Ws &w, const Root &R, uint32_t buf) {
+  if (buf == BUF_IN) return (uint32_t *)R.vin;
+  if (buf == BUF_OUT) return R.vout;
+  return w.tmpV + R.tmp_off;
+}
+
+AMS_DEV void push_leaf(const Ws &w, Seg s) {
+  uint32_t slot = atomicAdd(&w.ctr->nleaf, 1u);
+  if (slot < w.capLeaf) w.leaves[slot] = s; else atomicOr(&w.ctr->overflow, 1u);
+}
+
+// A root or child of N keys entering level lv: a leaf when it fits the base
+// case, an oversized leaf when no partition level is left, otherwise an
+// active subproblem of level lv.
+AMS_DEV void place_subproblem(const Ws &w, const LevTable &lt, uint32_t L, uint32_t lv,
+                              uint32_t off, uint32_t N, uint32_t root, uint32_t buf, bool inplace,
+                              uint32_t C) {
+  if (N == 0) return;
+  if (N <= C) {
+    push_leaf(w, Seg{off, N, root, make_meta(buf, LEAF_REG, 0, 0, 0)});
+    return;
+  }
+  if (lv >= L) {
+    push_leaf(w, Seg{off, N, root, make_meta(buf, LEAF_BIG, 0, 0, 0)});
+    return;
+  }
+  const Lev &l = lt.l[lv];
+  uint32_t logr, logm, S;
+  seg_shape(N, C, l.shrink != 0, l.rmax, l.b, l.a, l.Scap, logr, logm, S);
+  uint32_t slot = atomicAdd(&w.ctr->nact[lv], 1u);
+  Seg s{off, N, root, make_meta(buf, 0, dst_for(buf, inplace, L, lv), logm, logr)};
+  if (slot < w.capAct[lv]) w.act[lv][slot] = s; else atomicOr(&w.ctr->overflow, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// set-up
+// ---------------------------------------------------------------------------
+__global__ void k_reset(Ws w) {
+  uint32_t *p = (uint32_t *)w.ctr;
+  for (uint32_t i = threadIdx.x; i < sizeof(Ctr) / 4; i += blockDim.x) p[i] = 0;
+}
+
+// mode 0: one root given by value; 1: contiguous segments of base arrays at
+// device offsets; 2: root table already in the workspace.
+__global__ void k_init_roots(Ws w, LevTable lt, uint32_t L, uint32_t C, int mode, Root single,
+                             const char *kin, const uint32_t *vin, char *kout, uint32_t *vout,
+                             const uint64_t *offs, uint32_t kw) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < w.nroots;
+       i += gridDim.x * blockDim.x) {
+    Root R;
+    if (mode == 0) {
+      R = single;
+    } else if (mode == 1) {
+      uint64_t o = offs[i], e = offs[i + 1];
+      R.kin = kin + o * kw;
+      R.vin = vin ? vin + o : nullptr;
+      R.kout = kout + o * kw;
+      R.vout = vout ? vout + o : nullptr;
+      R.n = e - o;
+      R.tmp_off = o;
+    } else {
+      R = w.roots[i];
+    }
+    if (mode != 2) w.roots[i] = R;
+    place_subproblem(w, lt, L, 0, 0, (uint32_t)R.n, i, BUF_IN, root_inplace(R), C);
+  }
+}
+
+// Prefix sums over the active list of a level: tiles, tile blocks, sample blocks.
+__global__ void __launch_bounds__(1024) k_plan(Ws w, Lev lv) {
+  __shared__ uint32_t tmp[1024];
+  const uint32_t tid = threadIdx.x;
+  uint32_t n = w.ctr->nact[lv.level];
+  if (n > w.capAct[lv.level]) {
+    if (tid == 0) atomicOr(&w.ctr->overflow, 2u);
+    n = w.capAct[lv.level];
+  }
+  const Seg *act = w.act[lv.level];
+  for (uint32_t i = tid; i < n; i += 1024) {
+    Seg s = act[i];
+    uint32_t tiles = (s.size + lv.TC - 1) / lv.TC;
+    w.tileStart[i] = tiles;
+    w.blkStart[i] = (tiles + lv.TB - 1) / lv.TB;
+    uint32_t logr, logm, S;
+    seg_shape(s.size, lv.C, lv.shrink != 0, lv.rmax, lv.b, lv.a, lv.Scap, logr, logm, S);
+    w.sampStart[i] = S / 256;
+  }
+  __syncthreads();
+  uint32_t tt = block_exscan<1024>(w.tileStart, n, tmp);
+  uint32_t tb = block_exscan<1024>(w.blkStart, n, tmp);
+  uint32_t ts = block_exscan<1024>(w.sampStart, n, tmp);
+  if (tid == 0) {
+    w.tileStart[n] = tt;
+    w.blkStart[n] = tb;
+    w.sampStart[n] = ts;
+    // capacities are upper bounds by construction; if one were exceeded the
+    // level processes nothing (and the overflow flag is raised) rather than
+    // index past its tables
+    const bool over = tt > w.capTile || tb > w.capBlk || ts > w.capSBlk;
+    if (over) atomicOr(&w.ctr->overflow, 4u);
+    w.ctr->P = over ? 0 : n;
+    w.ctr->ntile = over ? 0 : tt;
+    w.ctr->nblk = over ? 0 : tb;
+    w.ctr->nsblk = over ? 0 : ts;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sample (Section 6: a random sample of a*b*r keys), ranked inside blocks of
+// 256 by comparing all pairs (Section 4.2), ties broken by sample index.
+// ---------------------------------------------------------------------------
+template <int KT> __global__ void __launch_bounds__(256) k_sample_blocks(Ws w, Lev lv) {
+  typedef typename Key<KT>::T K;
+  __shared__ K sh[256];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t P = w.ctr->P, total = w.ctr->nsblk;
+  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    uint32_t i = find_owner(w.sampStart, P, item);
+    uint32_t j = item - w.sampStart[i];
+    Seg s = w.act[lv.level][i];
+    Root R = w.roots[s.root];
+    uint32_t buf = seg_buf(s.meta);
+    const K *src = kptr<K>(w, R, buf) + s.off;
+    uint64_t st = stream_state(lv.seed, lv.level, s.root, s.off);
+    K x = src[draw_pos(st, j * 256 + tid, s.size)];
+    if (buf == BUF_IN) x = Key<KT>::enc(x);
+    sh[tid] = x;
+    __syncthreads();
+    uint32_t rank = 0;
+    for (uint32_t q = 0; q < 256; ++q) {
+      K y = sh[q];
+      rank += (uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(q < tid));
+    }
+    ((K *)w.samp)[(size_t)i * lv.Smax + j * 256 + rank] = x;
+    __syncthreads();
+  }
+}
+
+// Rank every sample element across the sorted blocks (binary search: the
+// merge step of Section 4.2; equal keys ordered by block, i.e. by sample
+// index) and write the element of rank j*a-1 as splitter j (j = 1..m-1)
+// into the sorted array and the Eytzinger tree.  Item = (subproblem, group
+// of rankG blocks); unused item slots exit at once.
+template <int KT> __global__ void __launch_bounds__(256) k_sample_rank(Ws w, Lev lv) {
+  typedef typename Key<KT>::T K;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  K *sh = (K *)smem_raw;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t P = w.ctr->P;
+  const uint32_t G = lv.rankG;
+  const uint32_t ngMax = (lv.Smax / 256 + G - 1) / G;
+  const uint32_t total = P * ngMax;
+  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    uint32_t i = item / ngMax, g = item - i * ngMax;
+    uint32_t nb = w.sampStart[i + 1] - w.sampStart[i];
+    if (g * G >= nb) continue;
+    Seg s = w.act[lv.level][i];
+    const uint32_t S = nb * 256;
+    const uint32_t m = 1u << meta_logm(s.meta);
+    const uint32_t a = S / m;
+    const K *src = (const K *)w.samp + (size_t)i * lv.Smax;
+    for (uint32_t q = tid; q < S; q += 256) sh[q] = src[q];
+    __syncthreads();
+    K *spl = (K *)w.spl + (size_t)i * lv.mmax;
+    K *tree = (K *)w.tree + (size_t)i * lv.mmax;
+    uint32_t jEnd = (g + 1) * G < nb ? (g + 1) * G : nb;
+    for (uint32_t j = g * G; j < jEnd; ++j) {
+      K x = sh[j * 256 + tid];
+      uint32_t rank = tid;
+      for (uint32_t jb = 0; jb < nb; ++jb) {
+        if (jb == j) continue;
+        const K *blk = sh + jb * 256;
+        rank += (jb < j) ? count_less_eq(blk, 256u, x) : count_less(blk, 256u, x);
+      }
+      if ((rank + 1) % a == 0) {
+        uint32_t sp = (rank + 1) / a;
+        if (sp >= 1 && sp <= m - 1) {
+          spl[sp - 1] = x;
+          tree[eytzinger_slot(sp, m)] = x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Splitters given by the caller (step entry point): sorted ord values.
+template <int KT> __global__ void k_set_splitters(Ws w, Lev lv, const void *given) {
+  typedef typename Key<KT>::T K;
+  if (w.ctr->P == 0) return;
+  Seg s = w.act[0][0];
+  uint32_t m = 1u << meta_logm(s.meta);
+  const K *g = (const K *)given;
+  K *spl = (K *)w.spl;
+  K *tree = (K *)w.tree;
+  for (uint32_t j = threadIdx.x; j + 1 < m; j += blockDim.x) {
+    spl[j] = g[j];
+    tree[eytzinger_slot(j + 1, m)] = g[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Classification and per-tile histograms (Section 6: partition into b*r
+// buckets; Appendix D: equality buckets when splitters repeat).
+// ---------------------------------------------------------------------------
+template <typename K>
+AMS_DEV bool load_tree(const Ws &w, const Lev &lv, uint32_t i, uint32_t m, K *sTree, K *sSpl) {
+  const K *gt = (const K *)w.tree + (size_t)i * lv.mmax;
+  const K *gs = (const K *)w.spl + (size_t)i * lv.mmax;
+  bool dup = false;
+  for (uint32_t j = threadIdx.x; j < m; j += blockDim.x) {
+    if (j >= 1) sTree[j] = gt[j];
+    if (j + 1 < m) {
+      K v = gs[j];
+      if (sSpl) sSpl[j] = v;
+      if (j + 2 < m && v == gs[j + 1]) dup = true;
+    }
+  }
+  return __syncthreads_or(dup ? 1 : 0) || (lv.flags & AMS_FLAG_EQ_ALWAYS);
+}
+
+template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
+  typedef typename Key<KT>::T K;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  K *sTree = (K *)smem_raw;
+  K *sSpl = sTree + lv.mmax;
+  uint32_t *sH = (uint32_t *)(sSpl + lv.mmax);  // 4 x NB
+  const uint32_t tid = threadIdx.x, wave = tid >> 6;
+  const uint32_t P = w.ctr->P;
+  ItemRange ir = xcd_items(w.ctr->ntile);
+  uint32_t cur = 0xFFFFFFFFu;
+  bool eq = false;
+  uint32_t logm = 0, m = 0;
+  for (uint32_t g = ir.first; g < ir.end; g += ir.step) {
+    uint32_t i = find_owner(w.tileStart, P, g);
+    uint32_t t = g - w.tileStart[i];
+    Seg s = w.act[lv.level][i];
+    if (i != cur) {
+      __syncthreads();
+      logm = meta_logm(s.meta);
+      m = 1u << logm;
+      eq = load_tree<K>(w, lv, i, m, sTree, sSpl);
+      cur = i;
+    }
+    const uint32_t NB = eq ? 2 * m - 1 : m;
+    for (uint32_t q = tid; q < 4 * NB; q += 256) sH[q] = 0;
+    __syncthreads();
+    Root R = w.roots[s.root];
+    uint32_t buf = seg_buf(s.meta);
+    const K *src = kptr<K>(w, R, buf) + s.off;
+    const bool enc = buf == BUF_IN;
+    uint32_t lo = t * lv.TC;
+    uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
+    uint32_t *myH = sH + wave * NB;
+    constexpr int U = 4;
+    for (uint32_t base = lo; base < hi; base += 256 * U) {
+      K xs[U];
+      bool v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        uint32_t p = base + u * 256 + tid;
+        v[u] = p < hi;
+        xs[u] = v[u] ? src[p] : (K)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (v[u]) {
+          K x = enc ? Key<KT>::enc(xs[u]) : xs[u];
+          atomicAdd(&myH[classify_id(x, sTree, sSpl, logm, eq)], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    uint32_t *gh = w.hist + (size_t)g * lv.HS;
+    for (uint32_t id = tid; id < NB; id += 256)
+      gh[id] = sH[id] + sH[NB + id] + sH[2 * NB + id] + sH[3 * NB + id];
+    if (t == 0 && tid == 0) w.eqOn[i] = eq ? 1 : 0;
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_block_reduce(Ws w, Lev lv) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t P = w.ctr->P, total = w.ctr->nblk;
+  for (uint32_t B = blockIdx.x; B < total; B += gridDim.x) {
+    uint32_t i = find_owner(w.blkStart, P, B);
+    uint32_t bb = B - w.blkStart[i];
+    uint32_t t0 = w.tileStart[i] + bb * lv.TB;
+    uint32_t t1 = t0 + lv.TB < w.tileStart[i + 1] ? t0 + lv.TB : w.tileStart[i + 1];
+    Seg s = w.act[lv.level][i];
+    uint32_t m = 1u << meta_logm(s.meta);
+    uint32_t NB = w.eqOn[i] ? 2 * m - 1 : m;
+    for (uint32_t id = tid; id < NB; id += 256) {
+      uint32_t sum = 0;
+      for (uint32_t t = t0; t < t1; ++t) sum += w.hist[(size_t)t * lv.HS + id];
+      w.blkHist[(size_t)B * lv.HS + id] = sum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bucket grouping (Section 6: scan the bucket sizes, open the next group
+// when the load would exceed L; smallest feasible L by search, optimal by the
+// section's lemma.  Appendix C: many candidates per round, the bounds moved to
+// the largest group of a feasible scan and to the smallest overflowing group
+// of an infeasible one).
+// ---------------------------------------------------------------------------
+struct Greedy {
+  bool feasible;
+  uint32_t maxG, zmin;
+};
+
+AMS_DEV Greedy greedy_scan(const uint32_t *wgt, uint32_t nb, uint32_t L, uint32_t r) {
+  uint32_t cur = 0, groups = 1, maxG = 0, zmin = 0xFFFFFFFFu;
+  for (uint32_t j = 0; j < nb; ++j) {
+    uint32_t wj = wgt[j];
+    if (cur + wj > L) {
+      zmin = min(zmin, cur + wj);
+      maxG = max(maxG, cur);
+      ++groups;
+      cur = wj;
+    } else {
+      cur += wj;
+    }
+  }
+  maxG = max(maxG, cur);
+  return Greedy{groups <= r, maxG, zmin};
+}
+
+// L* for weights wgt[0..nb) and at most r groups, by a block of NT threads.
+// red: 2*NT/64 words of LDS.
+template <int NT>
+AMS_DEV uint32_t optimal_load(const uint32_t *wgt, uint32_t nb, uint32_t r, uint32_t *red) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr uint32_t NW = NT / 64;
+  uint32_t W = 0, mx = 0;
+  for (uint32_t j = tid; j < nb; j += NT) {
+    W += wgt[j];
+    mx = max(mx, wgt[j]);
+  }
+  W = wave_sum(W);
+  mx = wave_max(mx);
+  if (lane == 0) {
+    red[wave] = W;
+    red[NW + wave] = mx;
+  }
+  __syncthreads();
+  W = 0;
+  mx = 0;
+  for (uint32_t q = 0; q < NW; ++q) {
+    W += red[q];
+    mx = max(mx, red[NW + q]);
+  }
+  __syncthreads();
+  uint32_t avg = (uint32_t)(((uint64_t)W + r - 1) / r);
+  uint32_t lo = max(mx, avg), hi = avg + mx;
+  while (lo < hi) {
+    uint32_t span = hi - lo;
+    bool active;
+    uint32_t cand;
+    if (span <= NT) {
+      active = tid < span;
+      cand = lo + tid;
+    } else {
+      active = true;
+      cand = lo + (uint32_t)(((uint64_t)span * (tid + 1)) / (NT + 1));
+    }
+    uint32_t newHi = 0xFFFFFFFFu, newLo = 0;
+    if (active) {
+      Greedy gr = greedy_scan(wgt, nb, cand, r);
+      if (gr.feasible) newHi = gr.maxG; else newLo = gr.zmin;
+    }
+    newHi = wave_min(newHi);
+    newLo = wave_max(newLo);
+    if (lane == 0) {
+      red[wave] = newHi;
+      red[NW + wave] = newLo;
+    }
+    __syncthreads();
+    for (uint32_t q = 0; q < NW; ++q) {
+      hi = min(hi, red[q]);
+      lo = max(lo, red[NW + q]);
+    }
+    __syncthreads();
+  }
+  return lo;
+}
+
+struct PackSmem {
+  uint32_t *tot, *wgt, *sz, *start, *tmp, *red;
+  uint16_t *first, *end;
+  uint8_t *fin, *kind;
+};
+
+AMS_DEV PackSmem pack_smem(unsigned char *base, uint32_t HS, uint32_t CH) {
+  PackSmem p;
+  p.tot = (uint32_t *)base;
+  p.wgt = p.tot + HS;
+  p.sz = p.wgt + HS;
+  p.start = p.sz + CH + 1;
+  p.tmp = p.start + CH + 1;
+  p.red = p.tmp + 256;
+  p.first = (uint16_t *)(p.red + 16);
+  p.end = p.first + CH + 1;
+  p.fin = (uint8_t *)(p.end + CH + 1);
+  p.kind = p.fin + HS;
+  return p;
+}
+
+// Children of one subproblem from its id totals (in p.tot), by thread 0:
+// greedy groups under L, cut at final equality buckets; returns the count.
+AMS_DEV uint32_t build_children(const PackSmem &p, uint32_t NB, uint32_t L, uint32_t CH) {
+  uint32_t cur = 0, pf = 0, psz = 0, nch = 0;
+  for (uint32_t j = 0; j < NB && nch + 2 < CH; ++j) {
+    uint32_t wj = p.wgt[j];
+    if (cur + wj > L) {
+      if (psz) {
+        p.first[nch] = pf; p.end[nch] = j; p.sz[nch] = psz; p.kind[nch] = CHILD_REG; ++nch;
+      }
+      pf = j;
+      psz = 0;
+      cur = 0;
+    }
+    cur += wj;
+    if (p.fin[j]) {
+      if (psz) {
+        p.first[nch] = pf; p.end[nch] = j; p.sz[nch] = psz; p.kind[nch] = CHILD_REG; ++nch;
+      }
+      p.first[nch] = j; p.end[nch] = j + 1; p.sz[nch] = p.tot[j]; p.kind[nch] = CHILD_FINAL; ++nch;
+      pf = j + 1;
+      psz = 0;
+    } else {
+      psz += p.tot[j];
+    }
+  }
+  if (psz && nch < CH) {
+    p.first[nch] = pf; p.end[nch] = NB; p.sz[nch] = psz; p.kind[nch] = CHILD_REG; ++nch;
+  }
+  return nch;
+}
+
+__global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint32_t HS = lv.HS, CH = lv.CH;
+  PackSmem p = pack_smem(smem_raw, HS, CH);
+  __shared__ uint32_t sN;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t P = w.ctr->P;
+  for (uint32_t i = blockIdx.x; i < P; i += gridDim.x) {
+    Seg s = w.act[lv.level][i];
+    Root R = w.roots[s.root];
+    const uint32_t m = 1u << meta_logm(s.meta);
+    const uint32_t r = 1u << meta_logr(s.meta);
+    const bool eq = w.eqOn[i] != 0;
+    const uint32_t NB = eq ? 2 * m - 1 : m;
+    const uint32_t b0 = w.blkStart[i], nbk = w.blkStart[i + 1] - b0;
+    for (uint32_t id = tid; id < NB; id += 256) {
+      uint32_t sum = 0;
+      for (uint32_t bb = 0; bb < nbk; ++bb) sum += w.blkHist[(size_t)(b0 + bb) * HS + id];
+      p.tot[id] = sum;
+    }
+    __syncthreads();
+    const uint32_t N = s.size;
+    const uint32_t tfin = (N + r - 1) / r;
+    for (uint32_t id = tid; id < NB; id += 256) {
+      bool fin = eq && (id & 1u) && p.tot[id] >= tfin;
+      p.fin[id] = fin ? 1 : 0;
+      p.wgt[id] = fin ? 0u : p.tot[id];
+    }
+    __syncthreads();
+    const uint32_t L = optimal_load<256>(p.wgt, NB, r, p.red);
+    if (tid == 0) {
+      uint32_t nch = build_children(p, NB, L, CH);
+      uint32_t got = 0;
+      for (uint32_t c = 0; c < nch; ++c) got += p.sz[c];
+      if (got != N) atomicOr(&w.ctr->overflow, 8u);  // cannot happen: nch <= 3r = CH
+      sN = nch;
+    }
+    __syncthreads();
+    const uint32_t nch = sN;
+    if (w.dbgHist && lv.level == 0 && i == 0) {
+      for (uint32_t id = tid; id < NB; id += 256) w.dbgHist[id] = p.tot[id];
+      for (uint32_t c = tid; c < nch; c += 256) {
+        w.dbgChildren[4 * c] = p.first[c];
+        w.dbgChildren[4 * c + 1] = p.end[c];
+        w.dbgChildren[4 * c + 2] = p.sz[c];
+        w.dbgChildren[4 * c + 3] = p.kind[c];
+      }
+      if (tid == 0) *w.dbgNChild = nch;
+    }
+    for (uint32_t c = tid; c < nch; c += 256) p.start[c] = p.sz[c];
+    __syncthreads();
+    block_exscan<256>(p.start, nch, p.tmp);
+    // table ranges: child c owns ids [first_c, first_{c+1}); ids of dropped
+    // empty pieces fall to the child before them (they hold no keys)
+    if (tid == 0) {
+      p.first[0] = 0;
+      p.first[nch] = (uint16_t)NB;
+    }
+    __syncthreads();
+    uint16_t *gF = w.cfirst + (size_t)i * (CH + 1);
+    uint32_t *gS = w.cstart + (size_t)i * (CH + 1);
+    uint8_t *gD = w.cdst + (size_t)i * CH;
+    uint16_t *gI = w.i2c + (size_t)i * HS;
+    const bool inplace = root_inplace(R);
+    const uint32_t srcbuf = seg_buf(s.meta), dst = seg_dst(s.meta);
+    const bool finToOut = srcbuf == BUF_TMP || (srcbuf == BUF_IN && !inplace);
+    for (uint32_t c = tid; c <= nch; c += 256) {
+      gF[c] = p.first[c];
+      if (c < nch) gS[c] = p.start[c];
+    }
+    for (uint32_t c = tid; c < nch; c += 256) {
+      for (uint32_t id = p.first[c]; id < p.first[c + 1]; ++id) gI[id] = (uint16_t)c;
+      const uint32_t off = s.off + p.start[c], size = p.sz[c];
+      uint32_t cd;
+      if (p.kind[c] == CHILD_REG) {
+        cd = dst;
+        place_subproblem(w, lt, lv.L, lv.level + 1, off, size, s.root, cd, inplace, lv.C);
+      } else {
+        cd = finToOut ? BUF_OUT : dst;
+        if (cd != BUF_OUT) {
+          uint32_t nc = (size + lv.C - 1) / lv.C;
+          uint32_t slot = atomicAdd(&w.ctr->nleaf, nc);
+          for (uint32_t q = 0; q < nc; ++q) {
+            uint32_t o = q * lv.C;
+            uint32_t sz = size - o < lv.C ? size - o : lv.C;
+            if (slot + q < w.capLeaf)
+              w.leaves[slot + q] = Seg{off + o, sz, s.root, make_meta(cd, LEAF_COPY, 0, 0, 0)};
+            else
+              atomicOr(&w.ctr->overflow, 1u);
+          }
+        }
+      }
+      gD[c] = (uint8_t)(cd | (p.kind[c] << 4));
+    }
+    if (tid == 0) w.nch[i] = nch;
+    // child offsets at the start of every tile block of this subproblem
+    for (uint32_t c = tid; c < nch; c += 256) {
+      uint32_t run = p.start[c];
+      const uint32_t f = p.first[c], e = p.first[c + 1];
+      for (uint32_t bb = 0; bb < nbk; ++bb) {
+        w.blkOff[(size_t)(b0 + bb) * CH + c] = run;
+        const uint32_t *bh = w.blkHist + (size_t)(b0 + bb) * HS;
+        for (uint32_t id = f; id < e; ++id) run += bh[id];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Grouping alone (step entry point): out[0] = L*, out[1] = groups,
+// out[2..] = group starts.
+__global__ void __launch_bounds__(256) k_pack_only(const uint32_t *wgt, uint32_t nb, uint32_t r,
+                                                   uint32_t *out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  uint32_t *sW = (uint32_t *)smem_raw;
+  __shared__ uint32_t red[16];
+  for (uint32_t j = threadIdx.x; j < nb; j += 256) sW[j] = wgt[j];
+  __syncthreads();
+  uint32_t L = optimal_load<256>(sW, nb, r, red);
+  if (threadIdx.x == 0) {
+    uint32_t cur = 0, g = 0;
+    out[2 + g++] = 0;
+    for (uint32_t j = 0; j < nb; ++j) {
+      if (cur + sW[j] > L) {
+        out[2 + g++] = j;
+        cur = 0;
+      }
+      cur += sW[j];
+    }
+    out[0] = L;
+    out[1] = g;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_tile_scan(Ws w, Lev lv) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t P = w.ctr->P, total = w.ctr->nblk;
+  for (uint32_t B = blockIdx.x; B < total; B += gridDim.x) {
+    uint32_t i = find_owner(w.blkStart, P, B);
+    uint32_t bb = B - w.blkStart[i];
+    uint32_t t0 = w.tileStart[i] + bb * lv.TB;
+    uint32_t t1 = t0 + lv.TB < w.tileStart[i + 1] ? t0 + lv.TB : w.tileStart[i + 1];
+    uint32_t nch = w.nch[i];
+    const uint16_t *tf = w.cfirst + (size_t)i * (lv.CH + 1);
+    for (uint32_t c = tid; c < nch; c += 256) {
+      uint32_t run = w.blkOff[(size_t)B * lv.CH + c];
+      const uint32_t f = tf[c], e = tf[c + 1];
+      for (uint32_t t = t0; t < t1; ++t) {
+        w.tileOff[(size_t)t * lv.CH + c] = run;
+        const uint32_t *h = w.hist + (size_t)t * lv.HS;
+        for (uint32_t id = f; id < e; ++id) run += h[id];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stable scatter (Section 6 data delivery to groups, here into HBM ranges;
+// the prefix sums of Section 4.3 give every tile's start in every child).
+// A tile is processed in chunks of 256*KPT keys: every wavefront takes a
+// contiguous quarter of the chunk, ranks its keys among equal children with
+// ballots (input order kept), the chunk is regrouped by child in LDS and
+// written out in runs.
+// ---------------------------------------------------------------------------
+template <int KT, bool PAY, int KPT>
+__global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
+  typedef typename Key<KT>::T K;
+  constexpr uint32_t CHK = 256 * KPT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint32_t CH = lv.CH;
+  K *sTree = (K *)smem_raw;                                  // mmax
+  K *stK = sTree + lv.mmax;                                  // CHK
+  uint32_t *stV = (uint32_t *)(stK + CHK);                   // CHK if PAY
+  uint16_t *stC = (uint16_t *)(stV + (PAY ? CHK : 0));       // CHK
+  uint16_t *sI2C = stC + CHK;                                // HS
+  uint32_t *sBase = (uint32_t *)(sI2C + lv.HS);              // CH
+  uint32_t *sL = sBase + CH;                                 // CH + 1
+  uint32_t *sTot = sL + CH + 1;                              // CH
+  uint32_t *sCnt = sTot + CH;                                // 4 * CH
+  uint32_t *sTmp = sCnt + 4 * CH;                            // 256
+  uint8_t *sCd = (uint8_t *)(sTmp + 256);                    // CH
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t P = w.ctr->P;
+  ItemRange ir = xcd_items(w.ctr->ntile);
+  uint32_t cur = 0xFFFFFFFFu, logm = 0, nch = 0, nbits = 0;
+  bool eq = false;
+  const K *gSpl = nullptr;
+  for (uint32_t g = ir.first; g < ir.end; g += ir.step) {
+    uint32_t i = find_owner(w.tileStart, P, g);
+    uint32_t t = g - w.tileStart[i];
+    Seg s = w.act[lv.level][i];
+    if (i != cur) {
+      __syncthreads();
+      logm = meta_logm(s.meta);
+      const uint32_t m = 1u << logm;
+      const K *gt = (const K *)w.tree + (size_t)i * lv.mmax;
+      for (uint32_t j = tid + 1; j < m; j += 256) sTree[j] = gt[j];
+      eq = w.eqOn[i] != 0;
+      nch = w.nch[i];
+      nbits = ilog2c(nch);
+      const uint32_t NB = eq ? 2 * m - 1 : m;
+      const uint16_t *gi = w.i2c + (size_t)i * lv.HS;
+      for (uint32_t j = tid; j < NB; j += 256) sI2C[j] = gi[j];
+      const uint8_t *gd = w.cdst + (size_t)i * CH;
+      for (uint32_t c = tid; c < nch; c += 256) sCd[c] = gd[c];
+      gSpl = (const K *)w.spl + (size_t)i * lv.mmax;
+      cur = i;
+    }
+    for (uint32_t c = tid; c < nch; c += 256) sBase[c] = w.tileOff[(size_t)g * CH + c];
+    Root R = w.roots[s.root];
+    const uint32_t buf = seg_buf(s.meta);
+    const K *src = kptr<K>(w, R, buf) + s.off;
+    const uint32_t *vsrc = PAY ? vptr(w, R, buf) + s.off : nullptr;
+    const bool enc = buf == BUF_IN;
+    const uint32_t lo = t * lv.TC;
+    const uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
+    for (uint32_t cb = lo; cb < hi; cb += CHK) {
+      for (uint32_t q = tid; q < 4 * CH; q += 256) sCnt[q] = 0;
+      __syncthreads();
+      K xk[KPT];
+      uint32_t xv[KPT];
+      uint32_t xcr[KPT];  // child << 16 | rank inside (wave, child)
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const uint32_t p = cb + wave * (CHK / 4) + k * 64 + lane;
+        const bool valid = p < hi;
+        K x = valid ? src[p] : (K)0;
+        if (enc) x = Key<KT>::enc(x);
+        uint32_t v = 0;
+        if (PAY) v = valid ? vsrc[p] : 0u;
+        uint32_t c = valid ? sI2C[classify_id(x, sTree, gSpl, logm, eq)] : 0u;
+        uint64_t peers = match_lanes(c, valid, nbits);
+        uint32_t below = bits_below(peers);
+        uint32_t r = 0;
+        if (valid) {
+          uint32_t *cnt = sCnt + wave * CH + c;
+          r = *cnt + below;
+          if (below == 0) *cnt = r + (uint32_t)__popcll(peers);
+        }
+        xk[k] = x;
+        xv[k] = v;
+        xcr[k] = (c << 16) | r;
+      }
+      __syncthreads();
+      for (uint32_t c = tid; c < nch; c += 256) {
+        uint32_t tot = sCnt[c] + sCnt[CH + c] + sCnt[2 * CH + c] + sCnt[3 * CH + c];
+        sTot[c] = tot;
+        sL[c] = tot;
+      }
+      __syncthreads();
+      block_exscan<256>(sL, nch, sTmp);
+      for (uint32_t c = tid; c < nch; c += 256) {
+        uint32_t run = sL[c];
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+          uint32_t v = sCnt[ww * CH + c];
+          sCnt[ww * CH + c] = run;
+          run += v;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const uint32_t p = cb + wave * (CHK / 4) + k * 64 + lane;
+        if (p < hi) {
+          const uint32_t c = xcr[k] >> 16;
+          const uint32_t q = sCnt[wave * CH + c] + (xcr[k] & 0xFFFFu);
+          stK[q] = xk[k];
+          stC[q] = (uint16_t)c;
+          if (PAY) stV[q] = xv[k];
+        }
+      }
+      __syncthreads();
+      const uint32_t cnt = hi - cb < CHK ? hi - cb : CHK;
+      for (uint32_t q = tid; q < cnt; q += 256) {
+        const uint32_t c = stC[q];
+        const uint32_t rel = sBase[c] + (q - sL[c]);
+        if (rel >= s.size) {  // defensive: tables inconsistent; never write outside
+          atomicOr(&w.ctr->overflow, 16u);
+          continue;
+        }
+        const uint32_t d = s.off + rel;
+        const uint32_t cd = sCd[c];
+        const uint32_t db = cd & 15u;
+        K x = stK[q];
+        if (cd >> 4) x = Key<KT>::dec(x);
+        kptr<K>(w, R, db)[d] = x;
+        if (PAY) vptr(w, R, db)[d] = stV[q];
+      }
+      __syncthreads();
+      for (uint32_t c = tid; c < nch; c += 256) sBase[c] += sTot[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Base case (Section 4.2 all-pairs ranking; Section 6 base case).
+// ---------------------------------------------------------------------------
+template <typename K> struct FinSmem {
+  K *B;
+  uint32_t *vB;
+  uint16_t *bid;
+  uint32_t *bstart;  // 2*FMAX + 1
+  uint32_t *cnt;     // 8 x (2*FMAX)
+  K *smp, *srt, *tree;
+  uint32_t *tmp;     // FIN_THREADS
+};
+
+template <typename K, bool PAY> AMS_DEV FinSmem<K> fin_smem(unsigned char *base, uint32_t C) {
+  FinSmem<K> f;
+  f.B = (K *)base;
+  f.vB = (uint32_t *)(f.B + C);
+  f.bid = (uint16_t *)(f.vB + (PAY ? C : 0));
+  f.bstart = (uint32_t *)(f.bid + C);
+  f.cnt = f.bstart + 2 * FMAX + 4;
+  f.smp = (K *)(f.cnt + 8 * 2 * FMAX);
+  f.srt = f.smp + FMAX;
+  f.tree = f.srt + FMAX;
+  f.tmp = (uint32_t *)(f.tree + FMAX);
+  return f;
+}
+
+template <typename K, bool PAY> __host__ inline size_t fin_smem_bytes(uint32_t C) {
+  return C * sizeof(K) + (PAY ? C * 4 : 0) + C * 2 + (2 * FMAX + 4) * 4 + 8 * 2 * FMAX * 4 +
+         3 * FMAX * sizeof(K) + FIN_THREADS * 4;
+}
+
+constexpr uint32_t FIN_KPT = CMAX / FIN_THREADS;  // 16
+constexpr uint32_t LEAF_STREAM = 0xFFu;
+
+// Sort s <= CMAX keys from src into dst inside one workgroup.  f-1 splitters
+// sampled from the input split it into about s/(cutoff/2) buckets in LDS
+// (stable, equality buckets if splitters repeat); every bucket is then
+// ordered by comparing all its pairs: rank(x_i) = #{j : x_j < x_i} +
+// #{j < i : x_j = x_i}, which keeps equal keys in input order.
+template <int KT, bool PAY>
+AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
+                      const typename Key<KT>::T *src, const uint32_t *vsrc, bool enc_in,
+                      typename Key<KT>::T *dst, uint32_t *vdst, bool dec_out, uint32_t s,
+                      uint32_t cutoff, uint64_t st) {
+  typedef typename Key<KT>::T K;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t f = 1;
+  if (s > cutoff) {
+    uint32_t tgt = cutoff / 2 > 4 ? cutoff / 2 : 4;
+    uint32_t need = (s + tgt - 1) / tgt;
+    f = 2;
+    while (f < need && f < FMAX) f <<= 1;
+  }
+  const uint32_t logf = ilog2c(f);
+  bool eq = false;
+  if (f > 1) {
+    if (tid < f - 1) {
+      K x = src[draw_pos(st, tid, s)];
+      sm.smp[tid] = enc_in ? Key<KT>::enc(x) : x;
+    }
+    __syncthreads();
+    if (tid < f - 1) {
+      K x = sm.smp[tid];
+      uint32_t rank = 0;
+      for (uint32_t q = 0; q < f - 1; ++q) {
+        K y = sm.smp[q];
+        rank += (uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(q < tid));
+      }
+      sm.srt[rank] = x;
+    }
+    __syncthreads();
+    bool dup = false;
+    if (tid < f - 1) {
+      sm.tree[eytzinger_slot(tid + 1, f)] = sm.srt[tid];
+      dup = (tid + 2 < f) && sm.srt[tid] == sm.srt[tid + 1];
+    }
+    eq = __syncthreads_or(dup ? 1 : 0) != 0;
+  }
+  const uint32_t NB = f == 1 ? 1 : (eq ? 2 * f - 1 : f);
+  const uint32_t nbits = ilog2c(NB);
+  for (uint32_t q = tid; q < 8 * NB; q += FIN_THREADS) sm.cnt[q] = 0;
+  __syncthreads();
+  const uint32_t nsteps = (s + 63) / 64, spw = (nsteps + 7) / 8;
+  K xk[FIN_KPT];
+  uint32_t xv[FIN_KPT];
+  uint32_t xir[FIN_KPT];
+#pragma unroll
+  for (uint32_t k = 0; k < FIN_KPT; ++k) {
+    const uint32_t p = (wave * spw + k) * 64 + lane;
+    const bool valid = k < spw && p < s;
+    K x = valid ? src[p] : (K)0;
+    if (enc_in) x = Key<KT>::enc(x);
+    uint32_t v = 0;
+    if (PAY) v = valid ? vsrc[p] : 0u;
+    uint32_t id = (valid && f > 1) ? classify_id(x, sm.tree, sm.srt, logf, eq) : 0u;
+    uint64_t peers = match_lanes(id, valid, nbits);
+    uint32_t below = bits_below(peers);
+    uint32_t r = 0;
+    if (valid) {
+      uint32_t *c = sm.cnt + wave * NB + id;
+      r = *c + below;
+      if (below == 0) *c = r + (uint32_t)__popcll(peers);
+    }
+    xk[k] = x;
+    xv[k] = v;
+    xir[k] = (id << 16) | r;
+  }
+  __syncthreads();
+  for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
+    uint32_t sum = 0;
+    for (uint32_t ww = 0; ww < 8; ++ww) sum += sm.cnt[ww * NB + id];
+    sm.bstart[id] = sum;
+  }
+  __syncthreads();
+  block_exscan<FIN_THREADS>(sm.bstart, NB, sm.tmp);
+  if (tid == 0) sm.bstart[NB] = s;
+  for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
+    uint32_t run = sm.bstart[id];
+    for (uint32_t ww = 0; ww < 8; ++ww) {
+      uint32_t v = sm.cnt[ww * NB + id];
+      sm.cnt[ww * NB + id] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < FIN_KPT; ++k) {
+    const uint32_t p = (wave * spw + k) * 64 + lane;
+    if (k < spw && p < s) {
+      const uint32_t id = xir[k] >> 16;
+      const uint32_t q = sm.cnt[wave * NB + id] + (xir[k] & 0xFFFFu);
+      sm.B[q] = xk[k];
+      sm.bid[q] = (uint16_t)id;
+      if (PAY) sm.vB[q] = xv[k];
+    }
+  }
+  __syncthreads();
+  uint32_t fpos[FIN_KPT];
+#pragma unroll
+  for (uint32_t k = 0; k < FIN_KPT; ++k) {
+    const uint32_t q = tid + FIN_THREADS * k;
+    if (q < s) {
+      const uint32_t id = sm.bid[q];
+      const uint32_t bs = sm.bstart[id], be = sm.bstart[id + 1];
+      const K x = sm.B[q];
+      uint32_t rk;
+      if (eq && (id & 1u)) {
+        rk = q - bs;  // equality bucket: equal keys, already in input order
+      } else {
+        rk = 0;
+        for (uint32_t j = bs; j < be; ++j) {
+          const K y = sm.B[j];
+          rk += (uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(j < q));
+        }
+      }
+      fpos[k] = bs + rk;
+      xk[k] = x;
+      if (PAY) xv[k] = sm.vB[q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < FIN_KPT; ++k) {
+    const uint32_t q = tid + FIN_THREADS * k;
+    if (q < s) {
+      sm.B[fpos[k]] = xk[k];
+      if (PAY) sm.vB[fpos[k]] = xv[k];
+    }
+  }
+  __syncthreads();
+  for (uint32_t q = tid; q < s; q += FIN_THREADS) {
+    K x = sm.B[q];
+    dst[q] = dec_out ? Key<KT>::dec(x) : x;
+    if (PAY) vdst[q] = sm.vB[q];
+  }
+  __syncthreads();
+}
+
+// Stable merge of sorted A[0..na) and B[0..nb) (A first on ties) into out,
+// split across the workgroup by output position (merge path).
+template <int KT, bool PAY>
+AMS_DEV void wg_merge(const typename Key<KT>::T *A, const uint32_t *vA, uint32_t na,
+                      const typename Key<KT>::T *B, const uint32_t *vB, uint32_t nb,
+                      typename Key<KT>::T *out, uint32_t *vout, bool dec_out) {
+  typedef typename Key<KT>::T K;
+  const uint32_t len = na + nb;
+  const uint32_t per = (len + FIN_THREADS - 1) / FIN_THREADS;
+  const uint32_t k0 = threadIdx.x * per < len ? threadIdx.x * per : len;
+  const uint32_t k1 = k0 + per < len ? k0 + per : len;
+  if (k0 >= k1) return;
+  // co-rank: number of A elements among the first k0 outputs
+  uint32_t lo = k0 > nb ? k0 - nb : 0, hi = k0 < na ? k0 : na;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (A[mid] <= B[k0 - mid - 1]) lo = mid + 1; else hi = mid;
+  }
+  uint32_t i = lo, j = k0 - lo;
+  for (uint32_t k = k0; k < k1; ++k) {
+    bool takeA = j >= nb || (i < na && A[i] <= B[j]);
+    K x;
+    uint32_t v = 0;
+    if (takeA) {
+      x = A[i];
+      if (PAY) v = vA[i];
+      ++i;
+    } else {
+      x = B[j];
+      if (PAY) v = vB[j];
+      ++j;
+    }
+    out[k] = dec_out ? Key<KT>::dec(x) : x;
+    if (PAY) vout[k] = v;
+  }
+}
+
+template <int KT, bool PAY>
+__global__ void __launch_bounds__(FIN_THREADS) k_finish(Ws w, uint32_t C, uint32_t cutoff,
+                                                        uint64_t seed) {
+  typedef typename Key<KT>::T K;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  FinSmem<K> sm = fin_smem<K, PAY>(smem_raw, C);
+  const uint32_t tid = threadIdx.x;
+  uint32_t nleaf = w.ctr->nleaf;
+  if (nleaf > w.capLeaf) nleaf = w.capLeaf;
+  for (uint32_t li = blockIdx.x; li < nleaf; li += gridDim.x) {
+    const Seg L = w.leaves[li];
+    const Root R = w.roots[L.root];
+    if ((uint64_t)L.off + L.size > R.n) {  // defensive: never touch memory outside the root
+      if (tid == 0) atomicOr(&w.ctr->overflow, 32u);
+      continue;
+    }
+    const uint32_t kind = seg_kind(L.meta), buf = seg_buf(L.meta);
+    const K *src = kptr<K>(w, R, buf) + L.off;
+    const uint32_t *vsrc = PAY ? vptr(w, R, buf) + L.off : nullptr;
+    K *dst = (K *)R.kout + L.off;
+    uint32_t *vdst = PAY ? R.vout + L.off : nullptr;
+    if (kind == LEAF_COPY) {
+      for (uint32_t q = tid; q < L.size; q += FIN_THREADS) {
+        dst[q] = Key<KT>::dec(src[q]);
+        if (PAY) vdst[q] = vsrc[q];
+      }
+      continue;
+    }
+    const uint64_t st = stream_state(seed, LEAF_STREAM, L.root, L.off);
+    if (kind == LEAF_REG) {
+      lds_sort<KT, PAY>(sm, src, vsrc, buf == BUF_IN, dst, vdst, true, L.size, cutoff, st);
+      continue;
+    }
+    // Oversized leaf (a group larger than LDS after the planned levels):
+    // sort runs of C keys in LDS, then merge pairs of runs, ping-ponging
+    // between this range of the TMP and OUT buffers so the last pass lands
+    // in OUT.
+    const uint32_t n = L.size;
+    const uint32_t runs = (n + C - 1) / C;
+    const uint32_t passes = ilog2c(runs);
+    K *bufK[2] = {kptr<K>(w, R, BUF_TMP) + L.off, kptr<K>(w, R, BUF_OUT) + L.off};
+    uint32_t *bufV[2] = {PAY ? vptr(w, R, BUF_TMP) + L.off : nullptr,
+                         PAY ? vptr(w, R, BUF_OUT) + L.off : nullptr};
+    uint32_t curb = (passes & 1u) ? 0u : 1u;  // run buffer: OUT after an even number of passes
+    for (uint32_t r = 0; r < runs; ++r) {
+      uint32_t o = r * C, sz = n - o < C ? n - o : C;
+      lds_sort<KT, PAY>(sm, src + o, PAY ? vsrc + o : nullptr, buf == BUF_IN, bufK[curb] + o,
+                        PAY ? bufV[curb] + o : nullptr, false, sz, cutoff,
+                        stream_state(seed, LEAF_STREAM, L.root, L.off + o));
+    }
+    for (uint32_t pz = 0; pz < passes; ++pz) {
+      const uint32_t width = C << pz;
+      const uint32_t nxt = curb ^ 1u;
+      const bool last = pz + 1 == passes;
+      for (uint32_t a = 0; a < n; a += 2 * width) {
+        uint32_t na = n - a < width ? n - a : width;
+        uint32_t nb = n - a - na < width ? n - a - na : width;
+        wg_merge<KT, PAY>(bufK[curb] + a, PAY ? bufV[curb] + a : nullptr, na,
+                          bufK[curb] + a + na, PAY ? bufV[curb] + a + na : nullptr, nb,
+                          bufK[nxt] + a, PAY ? bufV[nxt] + a : nullptr, last);
+      }
+      __syncthreads();
+      curb = nxt;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512];
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+const char *last_error() { return g_err; }
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t nroots,
+                     uint64_t n_single, const ams_params *p) {
+  memset(&pl, 0, sizeof pl);
+  if (kt != KT_U32 && kt != KT_U64 && kt != KT_F32) {
+    set_error("unknown key type %d", kt);
+    return AMS_EINVAL;
+  }
+  pl.kt = kt;
+  pl.pay = pay;
+  pl.kw = kt == KT_U64 ? 8 : 4;
+  pl.nroots = nroots;
+  uint64_t total = 0, mx = 0;
+  for (uint32_t i = 0; i < nroots; ++i) {
+    uint64_t n = sizes ? sizes[i] : n_single;
+    if (n >= (1ull << 32)) {
+      set_error("segment of %llu elements: sizes must be below 2^32", (unsigned long long)n);
+      return AMS_EUNSUPPORTED;
+    }
+    total += n;
+    mx = std::max(mx, n);
+  }
+  pl.ntotal = total;
+  pl.maxroot = mx;
+  uint32_t C = CMAX;
+  if (p && p->leaf_capacity) C = std::max<uint32_t>(64, std::min<uint32_t>(p->leaf_capacity, CMAX));
+  pl.C = C;
+  uint64_t keysBig = 0;
+  for (uint32_t i = 0; i < nroots; ++i) {
+    uint64_t n = sizes ? sizes[i] : n_single;
+    if (n > C) {
+      ++pl.nbig;
+      keysBig += n;
+    }
+  }
+  pl.cutoff = (p && p->base_cutoff) ? std::min<uint32_t>(std::max<uint32_t>(p->base_cutoff, 2), 1024) : 32;
+  pl.seed = (p && p->seed) ? p->seed : 14106754ull;
+  pl.flags = p ? p->flags : 0;
+  uint32_t r = (p && p->k) ? p->k : 256;
+  if (r < 2 || r > 1024 || (r & (r - 1))) {
+    set_error("k must be a power of two in 2..1024 (got %u)", r);
+    return AMS_EINVAL;
+  }
+  uint32_t b = (p && p->overpartition_b) ? p->overpartition_b : 4;
+  if (b < 1 || (b & (b - 1))) {
+    set_error("overpartition_b must be a power of two (got %u)", b);
+    return AMS_EINVAL;
+  }
+  if (r * b > 2048) b = std::max<uint32_t>(1, 2048 / r);
+  uint32_t TC = (p && p->tile_keys) ? p->tile_keys : 32768;
+  if (TC % 4096 || TC == 0) {
+    set_error("tile_keys must be a positive multiple of 4096 (got %u)", TC);
+    return AMS_EINVAL;
+  }
+  const uint32_t Scap = 65536 / pl.kw;
+  // levels: enough that an average group fits half of the leaf capacity
+  uint32_t L = 0;
+  if (mx > C) {
+    if (p && p->levels) {
+      L = std::min<uint32_t>(p->levels, MAXLEV);
+    } else {
+      L = 1;
+      double cap = (double)r;
+      while (L < MAXLEV && (double)mx / cap > C / 2.0) {
+        ++L;
+        cap *= r;
+      }
+    }
+  }
+  pl.L = L;
+  uint64_t P = pl.nbig, keys = keysBig;
+  uint64_t leaves = nroots + 64;
+  for (uint32_t l = 0; l < L; ++l) {
+    LevelShape &ls = pl.lev[l];
+    ls.rmax = r;
+    ls.b = b;
+    ls.a = (p && p->samples_per_bucket) ? p->samples_per_bucket : (l == 0 ? 8 : 4);
+    ls.mmax = std::min<uint32_t>(2048, r * b);
+    ls.Smax = (uint32_t)std::min<uint64_t>(Scap, align256((uint64_t)ls.a * ls.mmax));
+    if (ls.Smax < 256) ls.Smax = 256;
+    ls.TC = TC;
+    ls.TB = 64;
+    ls.HS = 2 * ls.mmax;
+    ls.CH = 3 * r;
+    ls.P = (uint32_t)std::max<uint64_t>(P, 1);
+    ls.tiles = (uint32_t)(keys / TC + P + 2);
+    ls.blocks = ls.tiles / ls.TB + (uint32_t)P + 2;
+    ls.sblocks = (uint32_t)(P * (ls.Smax / 256) + 1);
+    uint32_t nb = ls.Smax / 256;
+    uint64_t want = (P * nb + 1023) / 1024;
+    ls.rankG = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(nb, want));
+    leaves += P * ls.CH + keys / C + 2;
+    uint64_t nextP = std::min<uint64_t>(P * ls.CH, keys / (C + 1));
+    P = nextP;
+  }
+  pl.capLeaf = (uint32_t)std::min<uint64_t>(leaves + total / C + 2, 0xFFFFFFF0ull);
+  uint32_t capAct = 1, capTile = 1, capBlk = 1, capS = 1, maxHS = 2, maxCH = 3, maxM = 2, maxS = 256;
+  for (uint32_t l = 0; l < L; ++l) {
+    const LevelShape &ls = pl.lev[l];
+    capAct = std::max(capAct, ls.P);
+    capTile = std::max(capTile, ls.tiles);
+    capBlk = std::max(capBlk, ls.blocks);
+    capS = std::max(capS, ls.sblocks);
+    maxHS = std::max(maxHS, ls.HS);
+    maxCH = std::max(maxCH, ls.CH);
+    maxM = std::max(maxM, ls.mmax);
+    maxS = std::max(maxS, ls.Smax);
+  }
+  pl.capActMax = capAct;
+  pl.capTile = capTile;
+  pl.capBlk = capBlk;
+  pl.capSBlk = capS;
+  pl.maxHS = maxHS;
+  pl.maxCH = maxCH;
+  pl.maxM = maxM;
+  pl.maxS = maxS;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  pl.o_tmpK = take(L ? total * pl.kw : 0);
+  pl.o_tmpV = take(L && pay ? total * 4 : 0);
+  pl.o_roots = take((size_t)nroots * sizeof(Root));
+  pl.o_ctr = take(sizeof(Ctr));
+  for (uint32_t l = 0; l <= MAXLEV; ++l)
+    pl.o_act[l] = take(l < L ? (size_t)pl.lev[l].P * sizeof(Seg) : 0);
+  pl.o_leaves = take((size_t)pl.capLeaf * sizeof(Seg));
+  const bool any = L > 0;
+  pl.o_tileStart = take(any ? (size_t)(capAct + 1) * 4 : 0);
+  pl.o_blkStart = take(any ? (size_t)(capAct + 1) * 4 : 0);
+  pl.o_sampStart = take(any ? (size_t)(capAct + 1) * 4 : 0);
+  pl.o_samp = take(any ? (size_t)capAct * maxS * pl.kw : 0);
+  pl.o_spl = take(any ? (size_t)capAct * maxM * pl.kw : 0);
+  pl.o_tree = take(any ? (size_t)capAct * maxM * pl.kw : 0);
+  pl.o_eq = take(any ? capAct : 0);
+  pl.o_hist = take(any ? (size_t)capTile * maxHS * 4 : 0);
+  pl.o_blkHist = take(any ? (size_t)capBlk * maxHS * 4 : 0);
+  pl.o_blkOff = take(any ? (size_t)capBlk * maxCH * 4 : 0);
+  pl.o_tileOff = take(any ? (size_t)capTile * maxCH * 4 : 0);
+  pl.o_i2c = take(any ? (size_t)capAct * maxHS * 2 : 0);
+  pl.o_cfirst = take(any ? (size_t)capAct * (maxCH + 1) * 2 : 0);
+  pl.o_cstart = take(any ? (size_t)capAct * (maxCH + 1) * 4 : 0);
+  pl.o_cdst = take(any ? (size_t)capAct * maxCH : 0);
+  pl.o_nch = take(any ? (size_t)capAct * 4 : 0);
+  pl.o_dbg = take((size_t)(nroots + 1) * 8);  // batch offsets upload / step outputs
+  pl.bytes = o;
+  return AMS_OK;
+}
+
+static Ws carve(const Plan &pl, char *base) {
+  Ws w;
+  memset(&w, 0, sizeof w);
+  w.roots = (Root *)(base + pl.o_roots);
+  w.nroots = pl.nroots;
+  w.tmpK = base + pl.o_tmpK;
+  w.tmpV = (uint32_t *)(base + pl.o_tmpV);
+  w.ctr = (Ctr *)(base + pl.o_ctr);
+  for (uint32_t l = 0; l <= MAXLEV; ++l) {
+    w.act[l] = (Seg *)(base + pl.o_act[l]);
+    w.capAct[l] = l < pl.L ? pl.lev[l].P : 0;
+  }
+  w.leaves = (Seg *)(base + pl.o_leaves);
+  w.capLeaf = pl.capLeaf;
+  w.tileStart = (uint32_t *)(base + pl.o_tileStart);
+  w.blkStart = (uint32_t *)(base + pl.o_blkStart);
+  w.sampStart = (uint32_t *)(base + pl.o_sampStart);
+  w.samp = base + pl.o_samp;
+  w.spl = base + pl.o_spl;
+  w.tree = base + pl.o_tree;
+  w.eqOn = (uint8_t *)(base + pl.o_eq);
+  w.hist = (uint32_t *)(base + pl.o_hist);
+  w.blkHist = (uint32_t *)(base + pl.o_blkHist);
+  w.blkOff = (uint32_t *)(base + pl.o_blkOff);
+  w.tileOff = (uint32_t *)(base + pl.o_tileOff);
+  w.i2c = (uint16_t *)(base + pl.o_i2c);
+  w.cfirst = (uint16_t *)(base + pl.o_cfirst);
+  w.cstart = (uint32_t *)(base + pl.o_cstart);
+  w.cdst = (uint8_t *)(base + pl.o_cdst);
+  w.nch = (uint32_t *)(base + pl.o_nch);
+  w.capTile = pl.capTile;
+  w.capBlk = pl.capBlk;
+  w.capSBlk = pl.capSBlk;
+  return w;
+}
+
+static LevTable lev_table(const Plan &pl, bool shrink_last) {
+  LevTable lt;
+  memset(&lt, 0, sizeof lt);
+  for (uint32_t l = 0; l < pl.L; ++l) {
+    const LevelShape &ls = pl.lev[l];
+    Lev &v = lt.l[l];
+    v.level = l;
+    v.L = pl.L;
+    v.last = l + 1 == pl.L;
+    v.shrink = shrink_last && v.last;
+    v.rmax = ls.rmax;
+    v.b = ls.b;
+    v.a = ls.a;
+    v.mmax = ls.mmax;
+    v.Smax = ls.Smax;
+    v.TC = ls.TC;
+    v.TB = ls.TB;
+    v.HS = ls.HS;
+    v.CH = ls.CH;
+    v.rankG = ls.rankG;
+    v.C = pl.C;
+    v.flags = pl.flags;
+    v.Scap = 65536 / pl.kw;
+    v.seed = pl.seed;
+  }
+  return lt;
+}
+
+static uint32_t grid_for(uint64_t items, uint32_t cap) {
+  if (items < 1) items = 1;
+  uint64_t g = std::min<uint64_t>(items, cap);
+  if (g >= 8) g &= ~7ull;
+  return (uint32_t)g;
+}
+
+template <typename F> static void allow_lds(F *kernel, size_t bytes) {
+  static thread_local bool done = false;
+  (void)done;
+  (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)std::min<size_t>(bytes, 163840));
+}
+
+template <int KT, bool PAY>
+static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hipStream_t s,
+                            uint32_t *dbg_hist, uint32_t *dbg_children, uint32_t *dbg_nchild,
+                            const void *given, bool shrink_last) {
+  typedef typename Key<KT>::T K;
+  char *base = (char *)wsv;
+  Ws w = carve(pl, base);
+  w.dbgHist = dbg_hist;
+  w.dbgChildren = dbg_children;
+  w.dbgNChild = dbg_nchild;
+  LevTable lt = lev_table(pl, shrink_last);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w);
+  uint32_t gi = (uint32_t)std::min<uint64_t>((pl.nroots + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_init_roots, dim3(std::max(gi, 1u)), dim3(256), 0, s, w, lt, pl.L, pl.C,
+                     rs.mode, rs.single, rs.kin, rs.vin, rs.kout, rs.vout, rs.d_offsets, pl.kw);
+  for (uint32_t l = 0; l < pl.L; ++l) {
+    const LevelShape &ls = pl.lev[l];
+    const Lev &lv = lt.l[l];
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, w, lv);
+    if (given && l == 0) {
+      hipLaunchKernelGGL(k_set_splitters<KT>, dim3(1), dim3(256), 0, s, w, lv, given);
+    } else {
+      hipLaunchKernelGGL(k_sample_blocks<KT>, dim3(grid_for(ls.sblocks, 2048)), dim3(256), 0, s,
+                         w, lv);
+      size_t lds = (size_t)ls.Smax * sizeof(K);
+      allow_lds(k_sample_rank<KT>, lds);
+      uint32_t ng = (ls.Smax / 256 + ls.rankG - 1) / ls.rankG;
+      hipLaunchKernelGGL(k_sample_rank<KT>, dim3(grid_for((uint64_t)ls.P * ng, 1024)), dim3(256),
+                         lds, s, w, lv);
+    }
+    size_t ldsC = 2 * (size_t)ls.mmax * sizeof(K) + 4 * (size_t)ls.HS * 4;
+    allow_lds(k_count<KT>, ldsC);
+    hipLaunchKernelGGL(k_count<KT>, dim3(grid_for(ls.tiles, 1024)), dim3(256), ldsC, s, w, lv);
+    hipLaunchKernelGGL(k_block_reduce, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
+    size_t ldsP = (size_t)ls.HS * 4 * 2 + (size_t)(ls.CH + 1) * 4 * 2 + 256 * 4 + 16 * 4 +
+                  (size_t)(ls.CH + 1) * 2 * 2 + ls.HS + ls.CH + 64;
+    allow_lds(k_pack, ldsP);
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(ls.P, 1024)), dim3(256), ldsP, s, w, lv, lt);
+    hipLaunchKernelGGL(k_tile_scan, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
+    constexpr int KPT = PAY ? 8 : 16;
+    constexpr uint32_t CHK = 256 * KPT;
+    size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + (PAY ? CHK * 4 : 0) + CHK * 2 +
+                  (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + 4 + (size_t)ls.CH * 16 + 256 * 4 +
+                  ls.CH + 64;
+    allow_lds(k_scatter<KT, PAY, KPT>, ldsS);
+    hipLaunchKernelGGL((k_scatter<KT, PAY, KPT>), dim3(grid_for(ls.tiles, 512)), dim3(256), ldsS,
+                       s, w, lv);
+  }
+  if (!dbg_hist) {
+    size_t ldsF = fin_smem_bytes<K, PAY>(pl.C) + 64;
+    allow_lds(k_finish<KT, PAY>, ldsF);
+    hipLaunchKernelGGL((k_finish<KT, PAY>), dim3(grid_for(pl.capLeaf, 256)), dim3(FIN_THREADS),
+                       ldsF, s, w, pl.C, pl.cutoff, pl.seed);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("kernel launch failed: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  return AMS_OK;
+}
+
+ams_status run_plan_ex(const Plan &pl, void *ws, const RootSource &src, hipStream_t s,
+                       uint32_t *dbg_hist, uint32_t *dbg_children, uint32_t *dbg_nchild,
+                       const void *given_splitters, bool shrink_last) {
+#define AMS_RUN(KT_, PAY_)                                                                      \
+  return run_typed<KT_, PAY_>(pl, ws, src, s, dbg_hist, dbg_children, dbg_nchild,              \
+                              given_splitters, shrink_last)
+  if (pl.kt == KT_U32) { if (pl.pay) AMS_RUN(KT_U32, true); AMS_RUN(KT_U32, false); }
+  if (pl.kt == KT_U64) { if (pl.pay) AMS_RUN(KT_U64, true); AMS_RUN(KT_U64, false); }
+  if (pl.pay) AMS_RUN(KT_F32, true);
+  AMS_RUN(KT_F32, false);
+#undef AMS_RUN
+}
+
+ams_status run_plan(const Plan &pl, void *ws, const RootSource &src, hipStream_t s,
+                    uint32_t *dbg_hist, uint32_t *dbg_children, uint32_t *dbg_nchild,
+                    const void *given_splitters) {
+  return run_plan_ex(pl, ws, src, s, dbg_hist, dbg_children, dbg_nchild, given_splitters, true);
+}
+
+// Step entry point helpers -------------------------------------------------
+ams_status run_pack_only(const uint32_t *d_w, uint32_t nb, uint32_t r, uint32_t *d_out,
+                         hipStream_t s) {
+  size_t lds = (size_t)nb * 4 + 64;
+  allow_lds(k_pack_only, lds);
+  hipLaunchKernelGGL(k_pack_only, dim3(1), dim3(256), lds, s, d_w, nb, r, d_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("kernel launch failed: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  return AMS_OK;
+}
+
+// Copy the sorted splitters of the first active subproblem of level 0.
+ams_status copy_splitters(const Plan &pl, void *ws, void *d_out, uint32_t m, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(d_out, (char *)ws + pl.o_spl, (size_t)(m - 1) * pl.kw,
+                                hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) {
+    set_error("hipMemcpyAsync: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  return AMS_OK;
+}
+
+ams_status run_sample_only(const Plan &pl, void *wsv, const RootSource &rs, hipStream_t s) {
+  // levels up to the splitters of level 0 only
+  Plan p2 = pl;
+  (void)p2;
+  char *base = (char *)wsv;
+  Ws w = carve(pl, base);
+  LevTable lt = lev_table(pl, false);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w);
+  hipLaunchKernelGGL(k_init_roots, dim3(1), dim3(256), 0, s, w, lt, pl.L, pl.C, rs.mode,
+                     rs.single, rs.kin, rs.vin, rs.kout, rs.vout, rs.d_offsets, pl.kw);
+  const LevelShape &ls = pl.lev[0];
+  const Lev &lv = lt.l[0];
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, w, lv);
+  uint32_t ng = (ls.Smax / 256 + ls.rankG - 1) / ls.rankG;
+  if (pl.kt == KT_U64) {
+    hipLaunchKernelGGL(k_sample_blocks<KT_U64>, dim3(grid_for(ls.sblocks, 2048)), dim3(256), 0,
+                       s, w, lv);
+    size_t lds = (size_t)ls.Smax * 8;
+    allow_lds(k_sample_rank<KT_U64>, lds);
+    hipLaunchKernelGGL(k_sample_rank<KT_U64>, dim3(grid_for(ng, 1024)), dim3(256), lds, s, w, lv);
+  } else if (pl.kt == KT_U32) {
+    hipLaunchKernelGGL(k_sample_blocks<KT_U32>, dim3(grid_for(ls.sblocks, 2048)), dim3(256), 0,
+                       s, w, lv);
+    size_t lds = (size_t)ls.Smax * 4;
+    allow_lds(k_sample_rank<KT_U32>, lds);
+    hipLaunchKernelGGL(k_sample_rank<KT_U32>, dim3(grid_for(ng, 1024)), dim3(256), lds, s, w, lv);
+  } else {
+    hipLaunchKernelGGL(k_sample_blocks<KT_F32>, dim3(grid_for(ls.sblocks, 2048)), dim3(256), 0,
+                       s, w, lv);
+    size_t lds = (size_t)ls.Smax * 4;
+    allow_lds(k_sample_rank<KT_F32>, lds);
+    hipLaunchKernelGGL(k_sample_rank<KT_F32>, dim3(grid_for(ng, 1024)), dim3(256), lds, s, w, lv);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("kernel launch failed: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  return AMS_OK;
+}
+
+}  // namespace ams

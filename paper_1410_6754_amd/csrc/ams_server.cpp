@@ -1,0 +1,478 @@
+// Serving loop: continuous batching of independent sort requests.
+//
+// Requests (keys already in device memory) wait in a FIFO queue.  A scheduler
+// thread forms a batch from the oldest requests of one key type whenever a
+// worker stream is free, admitting each request only while the bytes it needs
+// (its result buffers plus its share of the batch workspace) fit the memory
+// budget; the batch runs through the same level kernels as ams_sort_batch,
+// with a root table that points at every request's own buffers.  Batches on
+// different streams overlap on the device.  Completion is observed through
+// events; results stay in server-owned device buffers until released.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ams.h"
+#include "ams_engine.h"
+
+namespace ams {
+ams_status run_plan_ex(const Plan &pl, void *ws, const RootSource &src, hipStream_t s,
+                       uint32_t *dbg_hist, uint32_t *dbg_children, uint32_t *dbg_nchild,
+                       const void *given_splitters, bool shrink_last);
+}
+
+using namespace ams;
+
+namespace {
+
+enum ReqState { PENDING = 0, RUNNING = 1, DONE = 2 };
+
+struct Request {
+  uint64_t ticket;
+  ams_key_t type;
+  const void *keys;
+  const uint32_t *vals;
+  uint64_t n;
+  void *out_k = nullptr;
+  uint32_t *out_v = nullptr;
+  size_t result_bytes = 0;
+  ReqState state = PENDING;
+  ams_req_stats st{};
+};
+
+struct Batch {
+  uint64_t id;
+  int stream;
+  std::vector<uint64_t> tickets;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  Root *h_roots = nullptr;  // pinned staging of the root table
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+double now_us(const std::chrono::steady_clock::time_point &t0) {
+  return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+}
+
+size_t kbytes(ams_key_t t) { return t == AMS_U64 ? 8 : 4; }
+
+}  // namespace
+
+struct ams_server {
+  int device = 0;
+  size_t budget = 0;
+  size_t reserved = 0;  // results of unreleased requests + workspaces of running batches
+  uint32_t max_pending = 4096;
+  std::vector<hipStream_t> streams;
+  std::vector<bool> busy;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<uint64_t> queue;  // pending tickets, FIFO
+  std::unordered_map<uint64_t, Request> reqs;
+  std::vector<Batch> running;
+  uint64_t next_ticket = 1, next_batch = 1;
+  uint32_t outstanding = 0;  // pending + running
+  bool stop = false;
+  std::thread worker;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  uint64_t max_batch_keys = 1ull << 28;
+  uint32_t max_batch_reqs = 1024;
+
+  size_t workspace_for(ams_key_t t, bool pay, const std::vector<uint64_t> &sizes) {
+    Plan pl;
+    if (make_plan(pl, (int)t, pay, sizes.data(), (uint32_t)sizes.size(), 0, nullptr)) return 0;
+    return pl.bytes;
+  }
+
+  size_t alone_need(const Request &r) {
+    std::vector<uint64_t> one{r.n};
+    return r.result_bytes + workspace_for(r.type, r.vals != nullptr, one);
+  }
+
+  // Called with mu held.  Forms and launches batches while a stream is free.
+  void schedule() {
+    for (;;) {
+      int free_s = -1;
+      for (size_t i = 0; i < streams.size(); ++i)
+        if (!busy[i]) {
+          free_s = (int)i;
+          break;
+        }
+      if (free_s < 0 || queue.empty()) return;
+      const Request &head = reqs[queue.front()];
+      const ams_key_t type = head.type;
+      const bool pay = head.vals != nullptr;
+      std::vector<uint64_t> pick, sizes;
+      size_t results = 0, ws = 0;
+      uint64_t keys = 0;
+      for (auto it = queue.begin(); it != queue.end(); ++it) {
+        Request &r = reqs[*it];
+        if (r.type != type || (r.vals != nullptr) != pay) continue;
+        if (!pick.empty() && (keys + r.n > max_batch_keys || pick.size() >= max_batch_reqs)) break;
+        sizes.push_back(r.n);
+        size_t w2 = workspace_for(type, pay, sizes);
+        if (reserved + results + r.result_bytes + w2 > budget) {
+          sizes.pop_back();
+          break;  // keep FIFO order: later requests wait with this one
+        }
+        pick.push_back(*it);
+        results += r.result_bytes;
+        ws = w2;
+        keys += r.n;
+      }
+      if (pick.empty()) return;  // not enough memory yet; retry when some frees
+      launch(free_s, type, pay, pick, ws, results);
+    }
+  }
+
+  void fail(Request &r, ams_status st) {
+    r.state = DONE;
+    r.st.status = st;
+    r.st.t_done_us = now_us(t0);
+    --outstanding;
+  }
+
+  void launch(int si, ams_key_t type, bool pay, const std::vector<uint64_t> &pick, size_t ws_bytes,
+              size_t results) {
+    hipStream_t s = streams[si];
+    Batch b;
+    b.id = next_batch++;
+    b.stream = si;
+    b.tickets = pick;
+    b.ws_bytes = ws_bytes;
+    const double ta = now_us(t0);
+    for (uint64_t t : pick) {
+      for (auto it = queue.begin(); it != queue.end(); ++it)
+        if (*it == t) {
+          queue.erase(it);
+          break;
+        }
+    }
+    // result buffers and workspace, stream-ordered
+    ams_status st = AMS_OK;
+    std::vector<uint64_t> sizes;
+    for (uint64_t t : pick) {
+      Request &r = reqs[t];
+      sizes.push_back(r.n);
+      r.st.t_admit_us = ta;
+      r.st.batch_id = b.id;
+      r.st.batch_size = (uint32_t)pick.size();
+      if (hipMallocAsync(&r.out_k, r.n * kbytes(type), s) != hipSuccess) st = AMS_ENOMEM;
+      if (pay && hipMallocAsync((void **)&r.out_v, r.n * 4, s) != hipSuccess) st = AMS_ENOMEM;
+    }
+    Plan pl;
+    if (!st) st = make_plan(pl, (int)type, pay, sizes.data(), (uint32_t)sizes.size(), 0, nullptr);
+    if (!st && hipMallocAsync(&b.ws, pl.bytes, s) != hipSuccess) st = AMS_ENOMEM;
+    if (!st && hipHostMalloc((void **)&b.h_roots, sizeof(Root) * pick.size(), 0) != hipSuccess)
+      st = AMS_ENOMEM;
+    if (!st) {
+      uint64_t off = 0;
+      for (size_t i = 0; i < pick.size(); ++i) {
+        Request &r = reqs[pick[i]];
+        Root R;
+        R.kin = r.keys;
+        R.vin = pay ? r.vals : nullptr;
+        R.kout = r.out_k;
+        R.vout = pay ? r.out_v : nullptr;
+        R.n = r.n;
+        R.tmp_off = off;
+        off += r.n;
+        b.h_roots[i] = R;
+      }
+      if (hipMemcpyAsync((char *)b.ws + pl.o_roots, b.h_roots, sizeof(Root) * pick.size(),
+                         hipMemcpyHostToDevice, s) != hipSuccess)
+        st = AMS_EHIP;
+    }
+    (void)hipEventCreate(&b.ev0);
+    (void)hipEventCreate(&b.ev1);
+    if (!st) {
+      (void)hipEventRecord(b.ev0, s);
+      RootSource rs;
+      memset(&rs, 0, sizeof rs);
+      rs.mode = 2;
+      st = run_plan_ex(pl, b.ws, rs, s, nullptr, nullptr, nullptr, nullptr, true);
+      (void)hipEventRecord(b.ev1, s);
+    }
+    const double tl = now_us(t0);
+    reserved += results + ws_bytes;
+    for (uint64_t t : pick) {
+      Request &r = reqs[t];
+      r.st.t_launch_us = tl;
+      if (st) {
+        fail(r, st);
+      } else {
+        r.state = RUNNING;
+      }
+    }
+    if (st) {
+      (void)hipStreamSynchronize(s);
+      finish_batch(b, false);
+      reserved -= ws_bytes;
+      cv_done.notify_all();
+      return;
+    }
+    busy[si] = true;
+    running.push_back(b);
+  }
+
+  void finish_batch(Batch &b, bool ok) {
+    if (ok) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, b.ev0, b.ev1);
+      const double td = now_us(t0);
+      for (uint64_t t : b.tickets) {
+        Request &r = reqs[t];
+        if (r.state == DONE) continue;
+        r.state = DONE;
+        r.st.status = AMS_OK;
+        r.st.t_done_us = td;
+        r.st.gpu_ms = ms;
+        --outstanding;
+      }
+    }
+    if (b.ws) (void)hipFreeAsync(b.ws, streams[b.stream]);
+    if (b.h_roots) (void)hipHostFree(b.h_roots);
+    if (b.ev0) (void)hipEventDestroy(b.ev0);
+    if (b.ev1) (void)hipEventDestroy(b.ev1);
+    b.ws = nullptr;
+    b.h_roots = nullptr;
+  }
+
+  // Called with mu held: retire finished batches.
+  bool reap() {
+    bool any = false;
+    for (size_t i = 0; i < running.size();) {
+      Batch &b = running[i];
+      hipError_t q = hipEventQuery(b.ev1);
+      if (q == hipErrorNotReady) {
+        ++i;
+        continue;
+      }
+      if (q != hipSuccess) {
+        for (uint64_t t : b.tickets) {
+          Request &r = reqs[t];
+          if (r.state != DONE) fail(r, AMS_EHIP);
+        }
+      }
+      finish_batch(b, q == hipSuccess);
+      reserved -= b.ws_bytes;
+      busy[b.stream] = false;
+      running.erase(running.begin() + i);
+      any = true;
+    }
+    return any;
+  }
+
+  void loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (!stop || !running.empty()) {
+      if (reap()) cv_done.notify_all();
+      if (!stop) schedule();
+      if (running.empty() && (queue.empty() || stop)) {
+        cv_work.wait_for(lk, std::chrono::milliseconds(5));
+      } else {
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        lk.lock();
+      }
+    }
+  }
+};
+
+extern "C" {
+
+ams_server *ams_server_create(int device, size_t hbm_budget, uint32_t max_pending,
+                              uint32_t n_streams, ams_status *st) {
+  if (st) *st = AMS_OK;
+  if (hipSetDevice(device) != hipSuccess) {
+    set_error("hipSetDevice(%d) failed", device);
+    if (st) *st = AMS_EHIP;
+    return nullptr;
+  }
+  ams_server *s = new ams_server();
+  s->device = device;
+  if (!hbm_budget) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      delete s;
+      set_error("hipMemGetInfo failed");
+      if (st) *st = AMS_EHIP;
+      return nullptr;
+    }
+    hbm_budget = fr / 10 * 8;
+  }
+  s->budget = hbm_budget;
+  s->max_pending = max_pending ? max_pending : 4096;
+  uint32_t ns = n_streams ? n_streams : 2;
+  for (uint32_t i = 0; i < ns; ++i) {
+    hipStream_t h;
+    if (hipStreamCreateWithFlags(&h, hipStreamNonBlocking) != hipSuccess) {
+      set_error("hipStreamCreate failed");
+      if (st) *st = AMS_EHIP;
+      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      delete s;
+      return nullptr;
+    }
+    s->streams.push_back(h);
+    s->busy.push_back(false);
+  }
+  s->worker = std::thread([s] { s->loop(); });
+  return s;
+}
+
+ams_status ams_submit(ams_server *srv, ams_key_t t, const void *d_keys, const uint32_t *d_vals,
+                      size_t n, uint64_t *ticket) {
+  if (!srv || !ticket || (t != AMS_U32 && t != AMS_U64 && t != AMS_F32) || (n && !d_keys)) {
+    set_error("bad arguments");
+    return AMS_EINVAL;
+  }
+  if (n >= (1ull << 32)) {
+    set_error("request of %zu keys: sizes must be below 2^32", n);
+    return AMS_EUNSUPPORTED;
+  }
+  std::unique_lock<std::mutex> lk(srv->mu);
+  if (srv->outstanding >= srv->max_pending) {
+    set_error("%u requests already pending or running", srv->outstanding);
+    return AMS_EAGAIN;
+  }
+  Request r;
+  r.ticket = srv->next_ticket++;
+  r.type = t;
+  r.keys = d_keys;
+  r.vals = d_vals;
+  r.n = n;
+  r.result_bytes = n * kbytes(t) + (d_vals ? n * 4 : 0);
+  r.st.n = n;
+  r.st.key_type = (int32_t)t;
+  r.st.t_submit_us = now_us(srv->t0);
+  if (srv->alone_need(r) > srv->budget) {
+    set_error("request needs %zu bytes, more than the %zu-byte budget", srv->alone_need(r),
+              srv->budget);
+    return AMS_ENOMEM;
+  }
+  *ticket = r.ticket;
+  if (n == 0) {
+    r.state = DONE;
+    r.st.t_admit_us = r.st.t_launch_us = r.st.t_done_us = r.st.t_submit_us;
+    srv->reqs[r.ticket] = r;
+    return AMS_OK;
+  }
+  srv->reqs[r.ticket] = r;
+  srv->queue.push_back(r.ticket);
+  ++srv->outstanding;
+  lk.unlock();
+  srv->cv_work.notify_one();
+  return AMS_OK;
+}
+
+ams_status ams_poll(ams_server *srv, uint64_t ticket, int *done, ams_req_stats *stats) {
+  if (!srv || !done) return AMS_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(ticket);
+  if (it == srv->reqs.end()) return AMS_ENOTFOUND;
+  *done = it->second.state == DONE;
+  if (stats) *stats = it->second.st;
+  return AMS_OK;
+}
+
+ams_status ams_wait(ams_server *srv, uint64_t ticket, ams_req_stats *stats) {
+  if (!srv) return AMS_EINVAL;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  for (;;) {
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return AMS_ENOTFOUND;
+    if (it->second.state == DONE) {
+      if (stats) *stats = it->second.st;
+      return it->second.st.status;
+    }
+    srv->cv_done.wait_for(lk, std::chrono::milliseconds(2));
+  }
+}
+
+ams_status ams_result(ams_server *srv, uint64_t ticket, void **d_keys, uint32_t **d_vals) {
+  if (!srv) return AMS_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(ticket);
+  if (it == srv->reqs.end()) return AMS_ENOTFOUND;
+  if (it->second.state != DONE) {
+    set_error("request %llu has not finished", (unsigned long long)ticket);
+    return AMS_EAGAIN;
+  }
+  if (d_keys) *d_keys = it->second.out_k;
+  if (d_vals) *d_vals = it->second.out_v;
+  return it->second.st.status;
+}
+
+ams_status ams_release(ams_server *srv, uint64_t ticket) {
+  if (!srv) return AMS_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(ticket);
+  if (it == srv->reqs.end()) return AMS_ENOTFOUND;
+  Request &r = it->second;
+  if (r.state != DONE) {
+    set_error("request %llu has not finished", (unsigned long long)ticket);
+    return AMS_EAGAIN;
+  }
+  hipStream_t s = srv->streams[0];
+  if (r.out_k) (void)hipFreeAsync(r.out_k, s);
+  if (r.out_v) (void)hipFreeAsync(r.out_v, s);
+  if (r.st.batch_id) srv->reserved -= r.result_bytes;
+  srv->reqs.erase(it);
+  srv->cv_work.notify_one();
+  return AMS_OK;
+}
+
+void ams_server_destroy(ams_server *srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+    // requests never launched end with AMS_EAGAIN
+    for (uint64_t t : srv->queue) srv->fail(srv->reqs[t], AMS_EAGAIN);
+    srv->queue.clear();
+  }
+  srv->cv_work.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  for (auto &kv : srv->reqs) {
+    if (kv.second.out_k) (void)hipFreeAsync(kv.second.out_k, srv->streams[0]);
+    if (kv.second.out_v) (void)hipFreeAsync(kv.second.out_v, srv->streams[0]);
+  }
+  for (hipStream_t s : srv->streams) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  delete srv;
+}
+
+ams_status ams_result_copy(ams_server *srv, uint64_t ticket, void *d_keys, uint32_t *d_vals,
+                           void *stream) {
+  void *k = nullptr;
+  uint32_t *v = nullptr;
+  ams_status st = ams_result(srv, ticket, &k, &v);
+  if (st) return st;
+  uint64_t n;
+  size_t kb;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    const Request &r = srv->reqs[ticket];
+    n = r.n;
+    kb = kbytes(r.type);
+  }
+  if (!n) return AMS_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (d_keys && hipMemcpyAsync(d_keys, k, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return AMS_EHIP;
+  if (d_vals && v && hipMemcpyAsync(d_vals, v, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return AMS_EHIP;
+  return AMS_OK;
+}
+
+}  // extern "C"

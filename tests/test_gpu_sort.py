@@ -1,0 +1,95 @@
+"""GPU parity: the HIP sort, through the C ABI, equals the oracle bit for bit.
+
+Sizes span the base case alone (n <= 8192), one partition level and two
+levels, with ragged tails; distributions cover uniform keys, heavy
+duplicates, Zipf, all-equal, sorted, reversed and float specials.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import check_sort_keys, check_sort_pairs, gen, log, to_dev, to_host
+from paper_1410_6754_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+U32, U64, F32 = W.KEY_U32, W.KEY_U64, W.KEY_F32
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1410_6754_amd import api as A
+    A.sort_keys  # noqa: B018
+    return A
+
+
+SMALL = [0, 1, 2, 3, 31, 63, 64, 65, 255, 1023, 1024, 1025, 4095, 8191, 8192]
+LEVEL = [8193, 20000, 65537, 300001]
+
+
+@pytest.mark.parametrize("kt", [U64, U32, F32])
+@pytest.mark.parametrize("n", SMALL)
+def test_base_case_sizes(api, kt, n):
+    log("base case kt=%d n=%d" % (kt, n))
+    check_sort_keys(api, kt, gen(kt, n, "uniform", n), what="kt%d n%d" % (kt, n))
+
+
+@pytest.mark.parametrize("kt", [U64, U32, F32])
+@pytest.mark.parametrize("n", LEVEL)
+def test_one_level_sizes(api, kt, n):
+    log("one level kt=%d n=%d" % (kt, n))
+    check_sort_keys(api, kt, gen(kt, n, "uniform", 100 + n), what="kt%d n%d" % (kt, n))
+
+
+@pytest.mark.parametrize("dist", ["few", "zipf", "equal", "sorted", "reversed", "specials"])
+@pytest.mark.parametrize("n", [5000, 100000])
+def test_distributions_u64(api, dist, n):
+    log("dist %s n=%d" % (dist, n))
+    check_sort_keys(api, U64, gen(U64, n, dist, 7), what=dist)
+
+
+@pytest.mark.parametrize("dist", ["few", "specials", "equal"])
+def test_distributions_f32(api, dist):
+    log("f32 dist %s" % dist)
+    check_sort_keys(api, F32, gen(F32, 70000, dist, 8), what=dist)
+
+
+@pytest.mark.parametrize("kt", [U64, U32, F32])
+@pytest.mark.parametrize("n", [1, 100, 8192, 50000])
+def test_pairs_stable(api, kt, n):
+    log("pairs kt=%d n=%d" % (kt, n))
+    check_sort_pairs(api, kt, gen(kt, n, "few", 9 + n), what="pairs")
+
+
+def test_pairs_hard_distributions(api):
+    for dist in ["zipf", "equal", "few", "reversed"]:
+        log("pairs dist %s" % dist)
+        check_sort_pairs(api, U64, gen(U64, 200000, dist, 10), what=dist)
+
+
+def test_two_levels(api):
+    n = (1 << 22) + 12345
+    log("two levels n=%d" % n)
+    check_sort_keys(api, U64, gen(U64, n, "uniform", 11), what="2lvl")
+
+
+def test_in_place(api):
+    keys = gen(U64, 100000, "uniform", 12)
+    import oracle
+    d = to_dev(keys)
+    api.sort_keys(d, out=d)
+    want, _ = oracle.oracle_sort(U64, keys)
+    assert np.array_equal(to_host(d), want)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    dk, dv = to_dev(keys), to_dev(vals)
+    api.sort_pairs(dk, dv, out_keys=dk, out_vals=dv)
+    wk, wv = oracle.oracle_sort(U64, keys, vals)
+    assert np.array_equal(to_host(dk), wk) and np.array_equal(to_host(dv), wv)
+
+
+def test_determinism(api):
+    keys = gen(U64, 300000, "few", 13)
+    d = to_dev(keys)
+    a = to_host(api.sort_keys(d))
+    b = to_host(api.sort_keys(d))
+    assert np.array_equal(a, b)
