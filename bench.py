@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X sample sort on the paper's workload shape.
+
+One step = one complete sort (every level and the base case) of one batch of
+synthetic keys already resident in HBM.  The default workload is n = 2^28
+uniform uint64 keys with two sample-sort levels of k = 256 groups and
+overpartitioning b = 4.  Prints ONE JSON line with the throughput, the
+roofline of the dominant kernel (timed live with HIP events on the sort's
+stream) and the oracle timed on the host.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1410_6754_amd import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+# name -> (n, key type, distribution, with payload, sort parameters, config index)
+WORKLOADS = {
+    "uniform_u64_2^28": (1 << 28, W.KEY_U64, "uniform", False,
+                         dict(levels=2, k=256, overpartition_b=4), 2),
+    "sorted_u64_2^28": (1 << 28, W.KEY_U64, "sorted", False,
+                        dict(levels=2, k=256, overpartition_b=4), 2),
+    "reversed_u64_2^28": (1 << 28, W.KEY_U64, "reversed", False,
+                          dict(levels=2, k=256, overpartition_b=4), 2),
+    "uniform_u64_2^20": (1 << 20, W.KEY_U64, "uniform", False,
+                         dict(levels=1, k=256, overpartition_b=1, samples_per_bucket=16), 1),
+    "pairs_few_2^27": (1 << 27, W.KEY_U64, "few", True, dict(), 3),
+    "pairs_zipf_2^27": (1 << 27, W.KEY_U64, "zipf", True, dict(), 3),
+    "pairs_equal_2^27": (1 << 27, W.KEY_U64, "equal", True, dict(), 3),
+}
+DEFAULT = "uniform_u64_2^28"
+
+
+def key_bytes(kt: int) -> int:
+    return 8 if kt == W.KEY_U64 else 4
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("ams_engine.hip", "ams_device.h"):
+        with open(os.path.join(ROOT, "paper_1410_6754_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d[workload][kernel]
+        if e.get("source_hash") != kernel_source_hash():
+            return None
+        return e["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def cpu_baseline(keys: np.ndarray, kt: int, vals, sample_n: int):
+    import oracle
+    sample = np.ascontiguousarray(keys[:sample_n])
+    sv = None if vals is None else np.ascontiguousarray(vals[:sample_n])
+    t0 = time.perf_counter()
+    oracle.oracle_sort(kt, sample, sv)
+    dt = time.perf_counter() - t0
+    return {"value": sample_n / dt / 1e9, "unit": "GKeys/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d keys of the workload (2^%d), one call of the oracle's "
+                      "textbook mergesort, single-threaded, %.2f s" % (sample_n, int(np.log2(sample_n)), dt)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
+    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--trace-file", default=None, help="write the per-kernel table here")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1410_6754_amd import api
+
+    n, kt, dist, pay, pkw, cfg = WORKLOADS[args.workload]
+    w = key_bytes(kt) + (4 if pay else 0)
+    print("bench: generating %s (n=%d)" % (args.workload, n), file=sys.stderr, flush=True)
+    rng = W.rng_for(cfg)
+    keys = W.keys(kt, n, rng, dist)
+    vals = np.arange(n, dtype=np.uint32) if pay else None
+
+    dev = torch.device("cuda:0")
+    d_keys = torch.from_numpy(keys).to(dev)
+    d_vals = torch.from_numpy(vals).to(dev) if pay else None
+    d_out = torch.empty_like(d_keys)
+    d_vout = torch.empty_like(d_vals) if pay else None
+    params = api.make_params(**pkw) if pkw else None
+    wsb = api.workspace_bytes(kt, n, pay, params)
+    ws = api.alloc_workspace(wsb, dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        if pay:
+            api.sort_pairs(d_keys, d_vals, d_out, d_vout, params=params, workspace=ws, stream=stream)
+        else:
+            api.sort_keys(d_keys, d_out, params=params, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("bench: warmup done", file=sys.stderr, flush=True)
+
+    # timed region: K steps between synchronisations; per-kernel events on the
+    # sort's stream give the dominant kernel's average launch duration
+    api.trace_start()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    trace = api.trace_stop()
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    print("bench: timed %d steps, %.3f ms/step (wall %.3f s)" % (args.steps, ms_per_step, wall),
+          file=sys.stderr, flush=True)
+
+    # correctness of the last output: sorted (ord order) -- cheap check on GPU
+    if kt == W.KEY_U64:
+        o = d_out.view(torch.int64) ^ torch.iinfo(torch.int64).min
+        verified = bool((o[1:] >= o[:-1]).all().item())
+    else:
+        verified = None
+
+    # per-kernel table (levels folded together)
+    per = {}
+    for e in trace:
+        base = e["name"].split(".")[0]
+        d = per.setdefault(base, {"launches": 0, "total_ms": 0.0})
+        d["launches"] += e["launches"]
+        d["total_ms"] += e["total_ms"]
+    alg_bytes = {"scatter": 2 * w * n, "finish": 2 * w * n, "count": key_bytes(kt) * n}
+    dom = max(per, key=lambda k: per[k]["total_ms"])
+    avg_ms = per[dom]["total_ms"] / per[dom]["launches"]
+    if dom in alg_bytes:
+        achieved = alg_bytes[dom] / (avg_ms * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom, args.workload),
+                "algorithmic_bytes_per_launch": alg_bytes[dom], "avg_launch_ms": round(avg_ms, 4)}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": None, "traffic": None, "avg_launch_ms": round(avg_ms, 4)}
+    kernels = {k: {"launches": v["launches"], "avg_ms": round(v["total_ms"] / v["launches"], 4),
+                   "share": round(v["total_ms"] / sum(x["total_ms"] for x in per.values()), 4)}
+               for k, v in sorted(per.items(), key=lambda kv: -kv[1]["total_ms"])}
+    if args.trace_file:
+        with open(args.trace_file, "w") as f:
+            json.dump({"workload": args.workload, "trace": trace, "kernels": kernels}, f, indent=1)
+
+    cpu = None
+    if not args.no_cpu:
+        sample_n = min(n, 1 << args.cpu_sample_log2)
+        print("bench: timing the oracle on %d keys" % sample_n, file=sys.stderr, flush=True)
+        cpu = cpu_baseline(keys, kt, vals, sample_n)
+
+    value = n / (ms_per_step * 1e-3) / 1e9
+    line = {
+        "metric": "GKeys/s & % HBM roofline (uint64, n=2^28); batched/served keys/s + p50/p99",
+        "value": round(value, 3),
+        "unit": "GKeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {W.KEY_U64: "u64", W.KEY_U32: "u32", W.KEY_F32: "f32"}[kt] + ("+u32" if pay else ""),
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "distribution": dist,
+                   "key": {W.KEY_U64: "uint64", W.KEY_U32: "uint32", W.KEY_F32: "float32"}[kt],
+                   "payload": "uint32" if pay else None, "params": pkw},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "verified_sorted": verified,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

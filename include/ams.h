@@ -115,6 +115,22 @@ ams_status ams_sort_batch(ams_key_t t, const void *d_kin, const uint32_t *d_vin,
 /* Message for the calling thread's most recent error ("" if none). */
 const char *ams_last_error(void);
 
+/* Per-kernel timing (tracing).  ams_trace_start() makes every later sort
+ * call of the calling thread bracket each kernel launch with a pair of
+ * hipEvents on the call's stream; ams_trace_stop() waits for them, sums the
+ * elapsed times per kernel name (name.L<level> for level kernels) into `out`
+ * (up to `max` entries) and returns the number of entries.  Tracing adds a
+ * few microseconds per launch. */
+typedef struct {
+  char name[32];
+  uint32_t launches;
+  uint32_t reserved;
+  double total_ms;
+  double max_ms;
+} ams_trace_entry;
+ams_status ams_trace_start(void);
+int ams_trace_stop(ams_trace_entry *out, int max);
+
 /* Library version string. */
 const char *ams_version(void);
 

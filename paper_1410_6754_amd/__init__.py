@@ -30,7 +30,8 @@ def __getattr__(name):
     # package (e.g. for the generators) does not import torch's GPU runtime
     if name in ("sort_keys", "sort_pairs", "sort_batch", "workspace_bytes",
                 "batch_workspace_bytes", "alloc_workspace", "make_params", "key_type_of",
-                "step_splitters", "step_level", "step_pack", "step_base_case", "KT_TO_DTYPE"):
+                "step_splitters", "step_level", "step_pack", "step_base_case", "KT_TO_DTYPE",
+                "trace_start", "trace_stop"):
         from . import api
         return getattr(api, name)
     if name == "Server":

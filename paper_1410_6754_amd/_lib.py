@@ -69,6 +69,17 @@ class ReqStats(ctypes.Structure):
     ]
 
 
+class TraceEntry(ctypes.Structure):
+    """Mirror of ams_trace_entry."""
+    _fields_ = [
+        ("name", ctypes.c_char * 32),
+        ("launches", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("total_ms", ctypes.c_double),
+        ("max_ms", ctypes.c_double),
+    ]
+
+
 # (name, restype, argtypes) of every exported symbol declared in include/ams.h
 _P = ctypes.c_void_p
 _U32 = ctypes.c_uint32
@@ -83,6 +94,8 @@ EXPORTS = [
     ("ams_sort_batch", _I, [_I, _P, _P, _P, _P, _P, _P, _SZ, _P, _SZ, _P, _P]),
     ("ams_last_error", ctypes.c_char_p, []),
     ("ams_version", ctypes.c_char_p, []),
+    ("ams_trace_start", _I, []),
+    ("ams_trace_stop", _I, [_P, _I]),
     ("ams_server_create", _P, [_I, _SZ, _U32, _U32, _P]),
     ("ams_submit", _I, [_P, _I, _P, _P, _SZ, _P]),
     ("ams_poll", _I, [_P, _U64, _P, _P]),

@@ -194,4 +194,19 @@ __all__ = [
     "AMS_U32", "AMS_U64", "AMS_F32", "KT_TO_DTYPE", "key_type_of", "make_params",
     "workspace_bytes", "batch_workspace_bytes", "alloc_workspace", "sort_keys", "sort_pairs",
     "sort_batch", "step_splitters", "step_level", "step_pack", "step_base_case", "_lib",
+    "trace_start", "trace_stop",
 ]
+
+
+def trace_start():
+    """Start per-kernel event timing for this thread's sort calls."""
+    check(lib().ams_trace_start())
+
+
+def trace_stop() -> list:
+    """Stop tracing; [{name, launches, total_ms, max_ms}] per kernel."""
+    n = lib().ams_trace_stop(None, 0)
+    arr = (_lib.TraceEntry * max(n, 1))()
+    n = lib().ams_trace_stop(arr, n)
+    return [{"name": arr[i].name.decode(), "launches": arr[i].launches,
+             "total_ms": arr[i].total_ms, "max_ms": arr[i].max_ms} for i in range(n)]

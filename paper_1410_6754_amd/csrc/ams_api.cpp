@@ -19,6 +19,8 @@ ams_status run_pack_only(const uint32_t *d_w, uint32_t nb, uint32_t r, uint32_t 
                          hipStream_t s);
 ams_status copy_splitters(const Plan &pl, void *ws, void *d_out, uint32_t m, hipStream_t s);
 ams_status run_sample_only(const Plan &pl, void *wsv, const RootSource &rs, hipStream_t s);
+ams_status trace_start();
+int trace_stop(ams_trace_entry *out, int max);
 }  // namespace ams
 
 using namespace ams;
@@ -98,6 +100,10 @@ extern "C" {
 const char *ams_last_error(void) { return ams::last_error(); }
 
 const char *ams_version(void) { return "ams-mi355x 0.1 (gfx950)"; }
+
+ams_status ams_trace_start(void) { return ams::trace_start(); }
+
+int ams_trace_stop(ams_trace_entry *out, int max) { return ams::trace_stop(out, max); }
 
 size_t ams_workspace_bytes(ams_key_t t, size_t n, int with_vals, const ams_params *p) {
   if (!valid_type(t)) return 0;

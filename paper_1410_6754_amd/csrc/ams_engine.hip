@@ -25,6 +25,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "ams_engine.h"
 
@@ -1166,6 +1167,83 @@ void set_error(const char *fmt, ...) {
 
 const char *last_error() { return g_err; }
 
+// ---------------------------------------------------------------------------
+// Kernel tracing: when on, every launch of the calling thread is bracketed by
+// a pair of events on the launch stream; ams_trace_stop sums them per kernel.
+// ---------------------------------------------------------------------------
+struct TraceRec {
+  char name[32];
+  hipEvent_t e0, e1;
+};
+static thread_local bool g_trace_on = false;
+static thread_local std::vector<TraceRec> *g_trace = nullptr;
+static thread_local std::vector<ams_trace_entry> *g_trace_acc = nullptr;
+
+struct TraceScope {
+  TraceRec rec;
+  bool on;
+  hipStream_t s;
+  TraceScope(const char *name, uint32_t level, hipStream_t st) : on(g_trace_on), s(st) {
+    if (!on) return;
+    if (level == 0xFFFFFFFFu) snprintf(rec.name, sizeof rec.name, "%s", name);
+    else snprintf(rec.name, sizeof rec.name, "%s.L%u", name, level);
+    (void)hipEventCreate(&rec.e0);
+    (void)hipEventCreate(&rec.e1);
+    (void)hipEventRecord(rec.e0, s);
+  }
+  ~TraceScope() {
+    if (!on) return;
+    (void)hipEventRecord(rec.e1, s);
+    g_trace->push_back(rec);
+  }
+};
+
+ams_status trace_start() {
+  if (!g_trace) g_trace = new std::vector<TraceRec>();
+  for (auto &r : *g_trace) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  g_trace->clear();
+  if (g_trace_acc) g_trace_acc->clear();
+  g_trace_on = true;
+  return AMS_OK;
+}
+
+// Aggregates pending records (waiting for their events) into per-name totals,
+// kept until the next trace_start; returns the number of names.
+int trace_stop(ams_trace_entry *out, int max) {
+  g_trace_on = false;
+  if (!g_trace_acc) g_trace_acc = new std::vector<ams_trace_entry>();
+  std::vector<ams_trace_entry> &acc = *g_trace_acc;
+  if (g_trace) {
+    for (auto &r : *g_trace) {
+      (void)hipEventSynchronize(r.e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, r.e0, r.e1);
+      ams_trace_entry *e = nullptr;
+      for (auto &a : acc)
+        if (!strcmp(a.name, r.name)) e = &a;
+      if (!e) {
+        ams_trace_entry z;
+        memset(&z, 0, sizeof z);
+        snprintf(z.name, sizeof z.name, "%s", r.name);
+        acc.push_back(z);
+        e = &acc.back();
+      }
+      e->launches += 1;
+      e->total_ms += ms;
+      if (ms > e->max_ms) e->max_ms = ms;
+      (void)hipEventDestroy(r.e0);
+      (void)hipEventDestroy(r.e1);
+    }
+    g_trace->clear();
+  }
+  if (out)
+    for (int i = 0; i < (int)acc.size() && i < max; ++i) out[i] = acc[i];
+  return (int)acc.size();
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t nroots,
@@ -1407,46 +1485,72 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
   w.dbgChildren = dbg_children;
   w.dbgNChild = dbg_nchild;
   LevTable lt = lev_table(pl, shrink_last);
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w);
+  { TraceScope ts("reset", 0xFFFFFFFFu, s); hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w); }
   uint32_t gi = (uint32_t)std::min<uint64_t>((pl.nroots + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_init_roots, dim3(std::max(gi, 1u)), dim3(256), 0, s, w, lt, pl.L, pl.C,
-                     rs.mode, rs.single, rs.kin, rs.vin, rs.kout, rs.vout, rs.d_offsets, pl.kw);
+  {
+    TraceScope ts("init", 0xFFFFFFFFu, s);
+    hipLaunchKernelGGL(k_init_roots, dim3(std::max(gi, 1u)), dim3(256), 0, s, w, lt, pl.L, pl.C,
+                       rs.mode, rs.single, rs.kin, rs.vin, rs.kout, rs.vout, rs.d_offsets, pl.kw);
+  }
   for (uint32_t l = 0; l < pl.L; ++l) {
     const LevelShape &ls = pl.lev[l];
     const Lev &lv = lt.l[l];
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, w, lv);
+    {
+      TraceScope ts("plan", l, s);
+      hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, w, lv);
+    }
     if (given && l == 0) {
       hipLaunchKernelGGL(k_set_splitters<KT>, dim3(1), dim3(256), 0, s, w, lv, given);
     } else {
-      hipLaunchKernelGGL(k_sample_blocks<KT>, dim3(grid_for(ls.sblocks, 2048)), dim3(256), 0, s,
-                         w, lv);
+      {
+        TraceScope ts("sample_blocks", l, s);
+        hipLaunchKernelGGL(k_sample_blocks<KT>, dim3(grid_for(ls.sblocks, 2048)), dim3(256), 0,
+                           s, w, lv);
+      }
       size_t lds = (size_t)ls.Smax * sizeof(K);
       allow_lds(k_sample_rank<KT>, lds);
       uint32_t ng = (ls.Smax / 256 + ls.rankG - 1) / ls.rankG;
+      TraceScope ts("sample_rank", l, s);
       hipLaunchKernelGGL(k_sample_rank<KT>, dim3(grid_for((uint64_t)ls.P * ng, 1024)), dim3(256),
                          lds, s, w, lv);
     }
     size_t ldsC = 2 * (size_t)ls.mmax * sizeof(K) + 4 * (size_t)ls.HS * 4;
     allow_lds(k_count<KT>, ldsC);
-    hipLaunchKernelGGL(k_count<KT>, dim3(grid_for(ls.tiles, 1024)), dim3(256), ldsC, s, w, lv);
-    hipLaunchKernelGGL(k_block_reduce, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
+    {
+      TraceScope ts("count", l, s);
+      hipLaunchKernelGGL(k_count<KT>, dim3(grid_for(ls.tiles, 1024)), dim3(256), ldsC, s, w, lv);
+    }
+    {
+      TraceScope ts("block_reduce", l, s);
+      hipLaunchKernelGGL(k_block_reduce, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
+    }
     size_t ldsP = (size_t)ls.HS * 4 * 2 + (size_t)(ls.CH + 1) * 4 * 2 + 256 * 4 + 16 * 4 +
                   (size_t)(ls.CH + 1) * 2 * 2 + ls.HS + ls.CH + 64;
     allow_lds(k_pack, ldsP);
-    hipLaunchKernelGGL(k_pack, dim3(grid_for(ls.P, 1024)), dim3(256), ldsP, s, w, lv, lt);
-    hipLaunchKernelGGL(k_tile_scan, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
+    {
+      TraceScope ts("pack", l, s);
+      hipLaunchKernelGGL(k_pack, dim3(grid_for(ls.P, 1024)), dim3(256), ldsP, s, w, lv, lt);
+    }
+    {
+      TraceScope ts("tile_scan", l, s);
+      hipLaunchKernelGGL(k_tile_scan, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
+    }
     constexpr int KPT = PAY ? 8 : 16;
     constexpr uint32_t CHK = 256 * KPT;
     size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + (PAY ? CHK * 4 : 0) + CHK * 2 +
                   (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + 4 + (size_t)ls.CH * 16 + 256 * 4 +
                   ls.CH + 64;
     allow_lds(k_scatter<KT, PAY, KPT>, ldsS);
-    hipLaunchKernelGGL((k_scatter<KT, PAY, KPT>), dim3(grid_for(ls.tiles, 512)), dim3(256), ldsS,
-                       s, w, lv);
+    {
+      TraceScope ts("scatter", l, s);
+      hipLaunchKernelGGL((k_scatter<KT, PAY, KPT>), dim3(grid_for(ls.tiles, 512)), dim3(256),
+                         ldsS, s, w, lv);
+    }
   }
   if (!dbg_hist) {
     size_t ldsF = fin_smem_bytes<K, PAY>(pl.C) + 64;
     allow_lds(k_finish<KT, PAY>, ldsF);
+    TraceScope ts("finish", 0xFFFFFFFFu, s);
     hipLaunchKernelGGL((k_finish<KT, PAY>), dim3(grid_for(pl.capLeaf, 256)), dim3(FIN_THREADS),
                        ldsF, s, w, pl.C, pl.cutoff, pl.seed);
   }
