@@ -226,6 +226,7 @@ ams_status ams_step_splitters(ams_key_t t, const void *d_keys, size_t n, uint32_
   p.samples_per_bucket = a;
   p.seed = seed ? seed : 14106754ull;
   p.leaf_capacity = 64;
+  p.flags = FLAG_NO_BASE_CASE;
   if (m > 1024) {  // k is limited to 1024: use b = 2
     p.k = m / 2;
     p.overpartition_b = 2;
@@ -277,7 +278,7 @@ ams_status ams_step_level(ams_key_t t, const void *d_in, void *d_out, size_t n,
   p.overpartition_b = m / r;
   p.samples_per_bucket = 1;
   p.leaf_capacity = 64;
-  p.flags = flags;
+  p.flags = flags | FLAG_NO_BASE_CASE;
   Plan pl;
   ams_status st = make_plan(pl, (int)t, false, nullptr, 1, n, &p);
   if (st) return st;

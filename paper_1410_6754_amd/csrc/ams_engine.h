@@ -16,6 +16,8 @@ constexpr uint32_t MAXLEV = 4;         // partition levels at most
 constexpr uint32_t CMAX = 8192;        // keys one base-case workgroup sorts in LDS
 constexpr uint32_t FIN_THREADS = 512;  // base-case workgroup size
 constexpr uint32_t FMAX = 256;         // largest in-LDS fan-out of the base case
+// internal plan flag: the caller runs only level steps, never the base case
+constexpr uint32_t FLAG_NO_BASE_CASE = 1u << 31;
 
 struct LevelShape {
   uint32_t rmax;     // groups per subproblem (paper's r)

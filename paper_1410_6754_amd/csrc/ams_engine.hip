@@ -873,43 +873,55 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
 // ---------------------------------------------------------------------------
 // Base case (Section 4.2 all-pairs ranking; Section 6 base case).
 // ---------------------------------------------------------------------------
+constexpr uint32_t FIN_KPT = CMAX / FIN_THREADS;  // 16 keys per thread
+constexpr uint32_t LEAF_STREAM = 0xFFu;
+
+// LDS of one base-case workgroup.  B holds the keys regrouped by bucket; the
+// sample, its sorted blocks and the splitter tree live inside B until the
+// keys are staged there.  Keys-only fits in 80 KiB (two workgroups per CU).
 template <typename K> struct FinSmem {
-  K *B;
-  uint32_t *vB;
-  uint16_t *bid;
-  uint32_t *bstart;  // 2*FMAX + 1
-  uint32_t *cnt;     // 8 x (2*FMAX)
-  K *smp, *srt, *tree;
-  uint32_t *tmp;     // FIN_THREADS
+  K *B;             // C keys
+  uint32_t *vB;     // C payloads (pairs only)
+  uint8_t *bid;     // C: bucket index b of each staged key (equality bit recomputed)
+  uint32_t *bstart; // 2*FMAX + 4 bucket starts
+  uint32_t *cnt;    // bucket counters (keys-only) or 8 per-wave rows (pairs)
+  uint32_t *tmp;    // FIN_THREADS words of scan scratch (aliases cnt for keys-only)
+  K *srt;           // FMAX sorted samples; srt[1..f-1] are the splitters
+  K *smp, *blk, *tree;  // overlays inside B: samples, block-sorted samples, tree
 };
+
+template <typename K, bool PAY> AMS_HD size_t fin_cnt_words() { return PAY ? 8 * 2 * FMAX : 2 * FMAX; }
 
 template <typename K, bool PAY> AMS_DEV FinSmem<K> fin_smem(unsigned char *base, uint32_t C) {
   FinSmem<K> f;
   f.B = (K *)base;
   f.vB = (uint32_t *)(f.B + C);
-  f.bid = (uint16_t *)(f.vB + (PAY ? C : 0));
-  f.bstart = (uint32_t *)(f.bid + C);
+  f.bid = (uint8_t *)(f.vB + (PAY ? C : 0));
+  f.bstart = (uint32_t *)(f.bid + ((C + 15) & ~15u));
   f.cnt = f.bstart + 2 * FMAX + 4;
-  f.smp = (K *)(f.cnt + 8 * 2 * FMAX);
-  f.srt = f.smp + FMAX;
-  f.tree = f.srt + FMAX;
-  f.tmp = (uint32_t *)(f.tree + FMAX);
+  f.tmp = PAY ? f.cnt + fin_cnt_words<K, PAY>() : f.cnt;
+  f.srt = (K *)(f.tmp + (PAY ? FIN_THREADS : fin_cnt_words<K, PAY>()));
+  f.smp = f.B;
+  f.blk = f.B + FMAX;
+  f.tree = f.B + 2 * FMAX;
   return f;
 }
 
 template <typename K, bool PAY> __host__ inline size_t fin_smem_bytes(uint32_t C) {
-  return C * sizeof(K) + (PAY ? C * 4 : 0) + C * 2 + (2 * FMAX + 4) * 4 + 8 * 2 * FMAX * 4 +
-         3 * FMAX * sizeof(K) + FIN_THREADS * 4;
+  return (size_t)C * sizeof(K) + (PAY ? (size_t)C * 4 : 0) + ((C + 15) & ~15u) +
+         (2 * FMAX + 4) * 4 + fin_cnt_words<K, PAY>() * 4 + (PAY ? FIN_THREADS * 4 : 0) +
+         FMAX * sizeof(K);
 }
 
-constexpr uint32_t FIN_KPT = CMAX / FIN_THREADS;  // 16
-constexpr uint32_t LEAF_STREAM = 0xFFu;
-
-// Sort s <= CMAX keys from src into dst inside one workgroup.  f-1 splitters
-// sampled from the input split it into about s/(cutoff/2) buckets in LDS
-// (stable, equality buckets if splitters repeat); every bucket is then
-// ordered by comparing all its pairs: rank(x_i) = #{j : x_j < x_i} +
-// #{j < i : x_j = x_i}, which keeps equal keys in input order.
+// Sort s <= C keys from src into dst inside one workgroup.
+//  1. f sampled keys are ranked: blocks of 64 by comparing all pairs, then
+//     across blocks by binary search (Section 4.2); srt[1..f-1] become the
+//     splitters of an f-way split (equality buckets if splitters repeat).
+//  2. Every key is classified and placed in LDS by bucket (keys-only: LDS
+//     atomics, order inside a bucket arbitrary since equal keys are equal
+//     bits; pairs: ballot ranks, input order kept).
+//  3. Every bucket is ordered by comparing all its pairs:
+//     rank(x_q) = #{j : x_j < x_q} + #{j < q : x_j = x_q}.
 template <int KT, bool PAY>
 AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
                       const typename Key<KT>::T *src, const uint32_t *vsrc, bool enc_in,
@@ -925,111 +937,173 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     while (f < need && f < FMAX) f <<= 1;
   }
   const uint32_t logf = ilog2c(f);
+  const K *spl = sm.srt + 1;  // spl[b] = splitter just above bucket b
   bool eq = false;
   if (f > 1) {
-    if (tid < f - 1) {
+    if (tid < f) {
       K x = src[draw_pos(st, tid, s)];
       sm.smp[tid] = enc_in ? Key<KT>::enc(x) : x;
     }
     __syncthreads();
-    if (tid < f - 1) {
-      K x = sm.smp[tid];
-      uint32_t rank = 0;
-      for (uint32_t q = 0; q < f - 1; ++q) {
-        K y = sm.smp[q];
-        rank += (uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(q < tid));
+    const uint32_t bsz = f < 64 ? f : 64, nbk = (f + 63) / 64;
+    if (tid < f) {
+      const uint32_t b0 = tid & ~63u;
+      const K x = sm.smp[tid];
+      uint32_t r = 0;
+      for (uint32_t q = 0; q < bsz; ++q) {
+        const K y = sm.smp[b0 + q];
+        r += (uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(b0 + q < tid));
       }
-      sm.srt[rank] = x;
+      sm.blk[b0 + r] = x;
+    }
+    __syncthreads();
+    if (tid < f) {
+      const uint32_t b = tid >> 6;
+      const K x = sm.blk[tid];
+      uint32_t r = tid & 63u;
+      for (uint32_t ob = 0; ob < nbk; ++ob) {
+        if (ob == b) continue;
+        r += ob < b ? count_less_eq(sm.blk + ob * 64, 64u, x) : count_less(sm.blk + ob * 64, 64u, x);
+      }
+      sm.srt[r] = x;
     }
     __syncthreads();
     bool dup = false;
-    if (tid < f - 1) {
-      sm.tree[eytzinger_slot(tid + 1, f)] = sm.srt[tid];
-      dup = (tid + 2 < f) && sm.srt[tid] == sm.srt[tid + 1];
+    if (tid >= 1 && tid < f) {
+      sm.tree[eytzinger_slot(tid, f)] = sm.srt[tid];
+      dup = tid + 1 < f && sm.srt[tid] == sm.srt[tid + 1];
     }
     eq = __syncthreads_or(dup ? 1 : 0) != 0;
   }
   const uint32_t NB = f == 1 ? 1 : (eq ? 2 * f - 1 : f);
-  const uint32_t nbits = ilog2c(NB);
-  for (uint32_t q = tid; q < 8 * NB; q += FIN_THREADS) sm.cnt[q] = 0;
-  __syncthreads();
-  const uint32_t nsteps = (s + 63) / 64, spw = (nsteps + 7) / 8;
   K xk[FIN_KPT];
   uint32_t xv[FIN_KPT];
-  uint32_t xir[FIN_KPT];
+  uint32_t xir[FIN_KPT];  // id << 16 | slot
+  if (!PAY) {
+    // ---- keys only: unstable split with LDS atomics ----
+    if (tid < NB) sm.cnt[tid] = 0;
+    __syncthreads();
 #pragma unroll
-  for (uint32_t k = 0; k < FIN_KPT; ++k) {
-    const uint32_t p = (wave * spw + k) * 64 + lane;
-    const bool valid = k < spw && p < s;
-    K x = valid ? src[p] : (K)0;
-    if (enc_in) x = Key<KT>::enc(x);
-    uint32_t v = 0;
-    if (PAY) v = valid ? vsrc[p] : 0u;
-    uint32_t id = (valid && f > 1) ? classify_id(x, sm.tree, sm.srt, logf, eq) : 0u;
-    uint64_t peers = match_lanes(id, valid, nbits);
-    uint32_t below = bits_below(peers);
-    uint32_t r = 0;
-    if (valid) {
-      uint32_t *c = sm.cnt + wave * NB + id;
-      r = *c + below;
-      if (below == 0) *c = r + (uint32_t)__popcll(peers);
+    for (uint32_t k = 0; k < FIN_KPT; ++k) {
+      const uint32_t p = tid + FIN_THREADS * k;
+      const bool valid = p < s;
+      K x = valid ? src[p] : (K)0;
+      if (enc_in) x = Key<KT>::enc(x);
+      xk[k] = x;
     }
-    xk[k] = x;
-    xv[k] = v;
-    xir[k] = (id << 16) | r;
-  }
-  __syncthreads();
-  for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
-    uint32_t sum = 0;
-    for (uint32_t ww = 0; ww < 8; ++ww) sum += sm.cnt[ww * NB + id];
-    sm.bstart[id] = sum;
-  }
-  __syncthreads();
-  block_exscan<FIN_THREADS>(sm.bstart, NB, sm.tmp);
-  if (tid == 0) sm.bstart[NB] = s;
-  for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
-    uint32_t run = sm.bstart[id];
-    for (uint32_t ww = 0; ww < 8; ++ww) {
-      uint32_t v = sm.cnt[ww * NB + id];
-      sm.cnt[ww * NB + id] = run;
-      run += v;
-    }
-  }
-  __syncthreads();
 #pragma unroll
-  for (uint32_t k = 0; k < FIN_KPT; ++k) {
-    const uint32_t p = (wave * spw + k) * 64 + lane;
-    if (k < spw && p < s) {
-      const uint32_t id = xir[k] >> 16;
-      const uint32_t q = sm.cnt[wave * NB + id] + (xir[k] & 0xFFFFu);
-      sm.B[q] = xk[k];
-      sm.bid[q] = (uint16_t)id;
-      if (PAY) sm.vB[q] = xv[k];
+    for (uint32_t k = 0; k < FIN_KPT; ++k) {
+      const uint32_t p = tid + FIN_THREADS * k;
+      uint32_t id = 0, slot = 0;
+      if (p < s) {
+        id = f > 1 ? classify_id(xk[k], sm.tree, spl, logf, eq) : 0u;
+        slot = atomicAdd(&sm.cnt[id], 1u);
+      }
+      xir[k] = (id << 16) | slot;
+    }
+    __syncthreads();
+    if (tid < NB) sm.bstart[tid] = sm.cnt[tid];
+    __syncthreads();
+    block_exscan<FIN_THREADS>(sm.bstart, NB, sm.tmp);
+    if (tid == 0) sm.bstart[NB] = s;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < FIN_KPT; ++k) {
+      const uint32_t p = tid + FIN_THREADS * k;
+      if (p < s) {
+        const uint32_t id = xir[k] >> 16;
+        const uint32_t q = sm.bstart[id] + (xir[k] & 0xFFFFu);
+        sm.B[q] = xk[k];
+        sm.bid[q] = (uint8_t)(eq ? id >> 1 : id);
+      }
+    }
+  } else {
+    // ---- pairs: stable split, waves own contiguous ranges, ballot ranks ----
+    const uint32_t nbits = ilog2c(NB);
+    for (uint32_t q = tid; q < 8 * NB; q += FIN_THREADS) sm.cnt[q] = 0;
+    __syncthreads();
+    const uint32_t nsteps = (s + 63) / 64, spw = (nsteps + 7) / 8;
+#pragma unroll
+    for (uint32_t k = 0; k < FIN_KPT; ++k) {
+      const uint32_t p = (wave * spw + k) * 64 + lane;
+      const bool valid = k < spw && p < s;
+      K x = valid ? src[p] : (K)0;
+      if (enc_in) x = Key<KT>::enc(x);
+      uint32_t v = valid ? vsrc[p] : 0u;
+      uint32_t id = (valid && f > 1) ? classify_id(x, sm.tree, spl, logf, eq) : 0u;
+      uint64_t peers = match_lanes(id, valid, nbits);
+      uint32_t below = bits_below(peers);
+      uint32_t r = 0;
+      if (valid) {
+        uint32_t *c = sm.cnt + wave * NB + id;
+        r = *c + below;
+        if (below == 0) *c = r + (uint32_t)__popcll(peers);
+      }
+      xk[k] = x;
+      xv[k] = v;
+      xir[k] = (id << 16) | r;
+    }
+    __syncthreads();
+    for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
+      uint32_t sum = 0;
+      for (uint32_t ww = 0; ww < 8; ++ww) sum += sm.cnt[ww * NB + id];
+      sm.bstart[id] = sum;
+    }
+    __syncthreads();
+    block_exscan<FIN_THREADS>(sm.bstart, NB, sm.tmp);
+    if (tid == 0) sm.bstart[NB] = s;
+    for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
+      uint32_t run = sm.bstart[id];
+      for (uint32_t ww = 0; ww < 8; ++ww) {
+        uint32_t v = sm.cnt[ww * NB + id];
+        sm.cnt[ww * NB + id] = run;
+        run += v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < FIN_KPT; ++k) {
+      const uint32_t p = (wave * spw + k) * 64 + lane;
+      if (k < spw && p < s) {
+        const uint32_t id = xir[k] >> 16;
+        const uint32_t q = sm.cnt[wave * NB + id] + (xir[k] & 0xFFFFu);
+        sm.B[q] = xk[k];
+        sm.bid[q] = (uint8_t)(eq ? id >> 1 : id);
+        sm.vB[q] = xv[k];
+      }
     }
   }
   __syncthreads();
+  // ---- all-pairs rank inside every bucket; waves run a common trip count ----
   uint32_t fpos[FIN_KPT];
 #pragma unroll
   for (uint32_t k = 0; k < FIN_KPT; ++k) {
     const uint32_t q = tid + FIN_THREADS * k;
-    if (q < s) {
-      const uint32_t id = sm.bid[q];
-      const uint32_t bs = sm.bstart[id], be = sm.bstart[id + 1];
-      const K x = sm.B[q];
-      uint32_t rk;
-      if (eq && (id & 1u)) {
-        rk = q - bs;  // equality bucket: equal keys, already in input order
-      } else {
-        rk = 0;
-        for (uint32_t j = bs; j < be; ++j) {
-          const K y = sm.B[j];
-          rk += (uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(j < q));
-        }
+    const bool valid = q < s;
+    const uint32_t qs = valid ? q : 0u;
+    const K x = sm.B[qs];
+    const uint32_t b = sm.bid[qs];
+    const uint32_t id = eq ? 2 * b + ((b + 1 < f && x == spl[b]) ? 1u : 0u) : b;
+    const uint32_t bs = valid ? sm.bstart[id] : 0u;
+    const uint32_t be = valid ? sm.bstart[id + 1] : 0u;
+    const bool isEq = eq && (id & 1u);  // equal keys, already in place order
+    const uint32_t len = (valid && !isEq) ? be - bs : 0u;
+    const uint32_t ml = wave_max(len);
+    uint32_t rk = 0;
+    for (uint32_t d = 0; d < ml; d += 4) {
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) {
+        const uint32_t dd = d + u;
+        const bool in = dd < len;
+        const uint32_t j = in ? bs + dd : qs;
+        const K y = sm.B[j];
+        rk += (uint32_t)in & ((uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(j < q)));
       }
-      fpos[k] = bs + rk;
-      xk[k] = x;
-      if (PAY) xv[k] = sm.vB[q];
     }
+    if (isEq) rk = q - bs;
+    fpos[k] = bs + rk;
+    xk[k] = x;
+    if (PAY) xv[k] = sm.vB[qs];
   }
   __syncthreads();
 #pragma unroll
@@ -1087,7 +1161,7 @@ AMS_DEV void wg_merge(const typename Key<KT>::T *A, const uint32_t *vA, uint32_t
 }
 
 template <int KT, bool PAY>
-__global__ void __launch_bounds__(FIN_THREADS) k_finish(Ws w, uint32_t C, uint32_t cutoff,
+__global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint32_t C, uint32_t cutoff,
                                                         uint64_t seed) {
   typedef typename Key<KT>::T K;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1270,7 +1344,12 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
   pl.ntotal = total;
   pl.maxroot = mx;
   uint32_t C = CMAX;
-  if (p && p->leaf_capacity) C = std::max<uint32_t>(64, std::min<uint32_t>(p->leaf_capacity, CMAX));
+  if (p && p->leaf_capacity) {
+    // the base case needs room for its sample overlays (3 * FMAX keys); step
+    // entry points that never run the base case may go lower
+    const uint32_t lo = (p->flags & FLAG_NO_BASE_CASE) ? 64 : 1024;
+    C = std::max<uint32_t>(lo, std::min<uint32_t>(p->leaf_capacity, CMAX) & ~15u);
+  }
   pl.C = C;
   uint64_t keysBig = 0;
   for (uint32_t i = 0; i < nroots; ++i) {
@@ -1548,11 +1627,11 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
     }
   }
   if (!dbg_hist) {
-    size_t ldsF = fin_smem_bytes<K, PAY>(pl.C) + 64;
+    size_t ldsF = fin_smem_bytes<K, PAY>(pl.C);
     allow_lds(k_finish<KT, PAY>, ldsF);
     TraceScope ts("finish", 0xFFFFFFFFu, s);
-    hipLaunchKernelGGL((k_finish<KT, PAY>), dim3(grid_for(pl.capLeaf, 256)), dim3(FIN_THREADS),
-                       ldsF, s, w, pl.C, pl.cutoff, pl.seed);
+    hipLaunchKernelGGL((k_finish<KT, PAY>), dim3(grid_for(pl.capLeaf, PAY ? 256 : 512)),
+                       dim3(FIN_THREADS), ldsF, s, w, pl.C, pl.cutoff, pl.seed);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
