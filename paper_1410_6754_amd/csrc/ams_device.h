@@ -162,6 +162,40 @@ AMS_DEV uint32_t classify_id(K x, const K *tree, const K *spl, uint32_t logm, bo
   return 2 * b + ((has_upper && x == up) ? 1u : 0u);
 }
 
+// Bucket ids of U keys at once: the descents advance level by level, so each
+// level issues U independent LDS reads.
+template <typename K, int U>
+AMS_DEV void classify_batch(const K (&x)[U], uint32_t (&id)[U], const K *tree, const K *spl,
+                            uint32_t logm, bool eq) {
+  uint32_t i[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) i[u] = 1;
+  for (uint32_t l = 0; l < logm; ++l) {
+    K t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = tree[i[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) i[u] = 2 * i[u] + (x[u] > t[u] ? 1u : 0u);
+  }
+  const uint32_t m = 1u << logm;
+  if (!eq) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) id[u] = i[u] - m;
+    return;
+  }
+  K up[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t b = i[u] - m;
+    up[u] = spl[b < m - 1 ? b : 0];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t b = i[u] - m;
+    id[u] = 2 * b + ((b < m - 1 && x[u] == up[u]) ? 1u : 0u);
+  }
+}
+
 // Number of elements < x (strict) or <= x in a sorted array of n = 2^k.
 template <typename K> AMS_DEV uint32_t count_less(const K *a, uint32_t n, K x) {
   uint32_t base = 0;
@@ -219,25 +253,40 @@ AMS_DEV uint32_t find_owner(const uint32_t *prefix, uint32_t n, uint32_t g) {
   return lo;
 }
 
-// In-place exclusive scan of a[0..n) by a block of NT threads; tmp holds NT
-// words of LDS.  Returns the total.  Ends with a barrier.
+// Inclusive prefix sum across the 64 lanes of a wavefront.
+AMS_DEV uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = __lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(v, d, 64);
+    if (lane >= (uint32_t)d) v += y;
+  }
+  return v;
+}
+
+// In-place exclusive scan of a[0..n) by a block of NT threads; tmp holds at
+// least NT/64 words of LDS.  Every thread scans a contiguous run, runs are
+// combined by a wavefront scan and one exchange of per-wave totals.  Returns
+// the total.  Ends with a barrier.
 template <int NT> AMS_DEV uint32_t block_exscan(uint32_t *a, uint32_t n, uint32_t *tmp) {
-  const uint32_t tid = threadIdx.x;
-  uint32_t per = (n + NT - 1) / NT;
-  uint32_t lo = tid * per < n ? tid * per : n;
-  uint32_t hi = lo + per < n ? lo + per : n;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  constexpr uint32_t NW = NT / 64;
+  const uint32_t per = (n + NT - 1) / NT;
+  const uint32_t lo = tid * per < n ? tid * per : n;
+  const uint32_t hi = lo + per < n ? lo + per : n;
   uint32_t s = 0;
   for (uint32_t i = lo; i < hi; ++i) s += a[i];
-  tmp[tid] = s;
+  const uint32_t incl = wave_incl_scan(s);
+  if (lane == 63) tmp[wave] = incl;
   __syncthreads();
-  for (uint32_t d = 1; d < (uint32_t)NT; d <<= 1) {
-    uint32_t v = tid >= d ? tmp[tid - d] : 0u;
-    __syncthreads();
-    tmp[tid] += v;
-    __syncthreads();
+  uint32_t off = 0, total = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < NW; ++w) {
+    const uint32_t t = tmp[w];
+    off += w < wave ? t : 0u;
+    total += t;
   }
-  uint32_t run = tid ? tmp[tid - 1] : 0u;
-  uint32_t total = tmp[NT - 1];
+  uint32_t run = off + incl - s;
   for (uint32_t i = lo; i < hi; ++i) {
     uint32_t v = a[i];
     a[i] = run;

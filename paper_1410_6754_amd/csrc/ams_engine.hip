@@ -55,7 +55,7 @@ struct Ws {
   uint32_t *tileStart, *blkStart, *sampStart;
   void *samp, *spl, *tree;
   uint8_t *eqOn;
-  uint32_t *hist, *blkHist, *blkOff, *tileOff;
+  uint32_t *hist, *blkHist, *totals, *tileOff;
   uint16_t *i2c, *cfirst;
   uint32_t *cstart;
   uint8_t *cdst;
@@ -355,13 +355,17 @@ AMS_DEV bool load_tree(const Ws &w, const Lev &lv, uint32_t i, uint32_t m, K *sT
   return __syncthreads_or(dup ? 1 : 0) || (lv.flags & AMS_FLAG_EQ_ALWAYS);
 }
 
+// Per-tile bucket counts.  One LDS histogram per workgroup (LDS atomics);
+// every thread keeps CU keys in flight so that enough loads are outstanding to
+// cover HBM latency.
 template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
   typedef typename Key<KT>::T K;
+  constexpr int CU = 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   K *sTree = (K *)smem_raw;
   K *sSpl = sTree + lv.mmax;
-  uint32_t *sH = (uint32_t *)(sSpl + lv.mmax);  // 4 x NB
-  const uint32_t tid = threadIdx.x, wave = tid >> 6;
+  uint32_t *sH = (uint32_t *)(sSpl + lv.mmax);  // NB
+  const uint32_t tid = threadIdx.x;
   const uint32_t P = w.ctr->P;
   ItemRange ir = xcd_items(w.ctr->ntile);
   uint32_t cur = 0xFFFFFFFFu;
@@ -379,7 +383,7 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
       cur = i;
     }
     const uint32_t NB = eq ? 2 * m - 1 : m;
-    for (uint32_t q = tid; q < 4 * NB; q += 256) sH[q] = 0;
+    for (uint32_t q = tid; q < NB; q += 256) sH[q] = 0;
     __syncthreads();
     Root R = w.roots[s.root];
     uint32_t buf = seg_buf(s.meta);
@@ -387,29 +391,28 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
     const bool enc = buf == BUF_IN;
     uint32_t lo = t * lv.TC;
     uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
-    uint32_t *myH = sH + wave * NB;
-    constexpr int U = 4;
-    for (uint32_t base = lo; base < hi; base += 256 * U) {
-      K xs[U];
-      bool v[U];
+    for (uint32_t base = lo; base < hi; base += 256 * CU) {
+      K xs[CU];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < CU; ++u) {
         uint32_t p = base + u * 256 + tid;
-        v[u] = p < hi;
-        xs[u] = v[u] ? src[p] : (K)0;
+        xs[u] = p < hi ? src[p] : (K)0;
       }
+      if (enc) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (v[u]) {
-          K x = enc ? Key<KT>::enc(xs[u]) : xs[u];
-          atomicAdd(&myH[classify_id(x, sTree, sSpl, logm, eq)], 1u);
-        }
+        for (int u = 0; u < CU; ++u) xs[u] = Key<KT>::enc(xs[u]);
+      }
+      uint32_t ids[CU];
+      classify_batch<K, CU>(xs, ids, sTree, sSpl, logm, eq);
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        uint32_t p = base + u * 256 + tid;
+        if (p < hi) atomicAdd(&sH[ids[u]], 1u);
       }
     }
     __syncthreads();
     uint32_t *gh = w.hist + (size_t)g * lv.HS;
-    for (uint32_t id = tid; id < NB; id += 256)
-      gh[id] = sH[id] + sH[NB + id] + sH[2 * NB + id] + sH[3 * NB + id];
+    for (uint32_t id = tid; id < NB; id += 256) gh[id] = sH[id];
     if (t == 0 && tid == 0) w.eqOn[i] = eq ? 1 : 0;
     __syncthreads();
   }
@@ -431,6 +434,41 @@ __global__ void __launch_bounds__(256) k_block_reduce(Ws w, Lev lv) {
       for (uint32_t t = t0; t < t1; ++t) sum += w.hist[(size_t)t * lv.HS + id];
       w.blkHist[(size_t)B * lv.HS + id] = sum;
     }
+  }
+}
+
+// Per subproblem and bucket id: exclusive prefix over its tile blocks (in
+// place in blkHist) and the total (bucket size).  Item = (subproblem, 256 ids).
+__global__ void __launch_bounds__(256) k_block_scan(Ws w, Lev lv) {
+  const uint32_t P = w.ctr->P;
+  const uint32_t chunks = (lv.HS + 255) / 256;
+  const uint32_t total = P * chunks;
+  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const uint32_t i = item / chunks;
+    const uint32_t id = (item - i * chunks) * 256 + threadIdx.x;
+    const uint32_t m = 1u << meta_logm(w.act[lv.level][i].meta);
+    const uint32_t NB = w.eqOn[i] ? 2 * m - 1 : m;
+    if (id >= NB) continue;
+    const uint32_t b0 = w.blkStart[i], nbk = w.blkStart[i + 1] - b0;
+    uint32_t *col = w.blkHist + (size_t)b0 * lv.HS + id;
+    uint32_t run = 0;
+    uint32_t bb = 0;
+    for (; bb + 8 <= nbk; bb += 8) {
+      uint32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = col[(size_t)(bb + u) * lv.HS];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        col[(size_t)(bb + u) * lv.HS] = run;
+        run += v[u];
+      }
+    }
+    for (; bb < nbk; ++bb) {
+      uint32_t v = col[(size_t)bb * lv.HS];
+      col[(size_t)bb * lv.HS] = run;
+      run += v;
+    }
+    w.totals[(size_t)i * lv.HS + id] = run;
   }
 }
 
@@ -589,12 +627,7 @@ __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
     const uint32_t r = 1u << meta_logr(s.meta);
     const bool eq = w.eqOn[i] != 0;
     const uint32_t NB = eq ? 2 * m - 1 : m;
-    const uint32_t b0 = w.blkStart[i], nbk = w.blkStart[i + 1] - b0;
-    for (uint32_t id = tid; id < NB; id += 256) {
-      uint32_t sum = 0;
-      for (uint32_t bb = 0; bb < nbk; ++bb) sum += w.blkHist[(size_t)(b0 + bb) * HS + id];
-      p.tot[id] = sum;
-    }
+    for (uint32_t id = tid; id < NB; id += 256) p.tot[id] = w.totals[(size_t)i * HS + id];
     __syncthreads();
     const uint32_t N = s.size;
     const uint32_t tfin = (N + r - 1) / r;
@@ -670,16 +703,6 @@ __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
       gD[c] = (uint8_t)(cd | (p.kind[c] << 4));
     }
     if (tid == 0) w.nch[i] = nch;
-    // child offsets at the start of every tile block of this subproblem
-    for (uint32_t c = tid; c < nch; c += 256) {
-      uint32_t run = p.start[c];
-      const uint32_t f = p.first[c], e = p.first[c + 1];
-      for (uint32_t bb = 0; bb < nbk; ++bb) {
-        w.blkOff[(size_t)(b0 + bb) * CH + c] = run;
-        const uint32_t *bh = w.blkHist + (size_t)(b0 + bb) * HS;
-        for (uint32_t id = f; id < e; ++id) run += bh[id];
-      }
-    }
     __syncthreads();
   }
 }
@@ -719,9 +742,12 @@ __global__ void __launch_bounds__(256) k_tile_scan(Ws w, Lev lv) {
     uint32_t t1 = t0 + lv.TB < w.tileStart[i + 1] ? t0 + lv.TB : w.tileStart[i + 1];
     uint32_t nch = w.nch[i];
     const uint16_t *tf = w.cfirst + (size_t)i * (lv.CH + 1);
+    const uint32_t *cs = w.cstart + (size_t)i * (lv.CH + 1);
+    const uint32_t *pre = w.blkHist + (size_t)B * lv.HS;  // prefix over earlier blocks
     for (uint32_t c = tid; c < nch; c += 256) {
-      uint32_t run = w.blkOff[(size_t)B * lv.CH + c];
       const uint32_t f = tf[c], e = tf[c + 1];
+      uint32_t run = cs[c];
+      for (uint32_t id = f; id < e; ++id) run += pre[id];
       for (uint32_t t = t0; t < t1; ++t) {
         w.tileOff[(size_t)t * lv.CH + c] = run;
         const uint32_t *h = w.hist + (size_t)t * lv.HS;
@@ -803,9 +829,17 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
         const bool valid = p < hi;
         K x = valid ? src[p] : (K)0;
         if (enc) x = Key<KT>::enc(x);
-        uint32_t v = 0;
-        if (PAY) v = valid ? vsrc[p] : 0u;
-        uint32_t c = valid ? sI2C[classify_id(x, sTree, gSpl, logm, eq)] : 0u;
+        xk[k] = x;
+        if (PAY) xv[k] = valid ? vsrc[p] : 0u;
+      }
+      classify_batch<K, KPT>(xk, xcr, sTree, gSpl, logm, eq);
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const uint32_t p = cb + wave * (CHK / 4) + k * 64 + lane;
+        const bool valid = p < hi;
+        const K x = xk[k];
+        const uint32_t v = xv[k];
+        uint32_t c = valid ? sI2C[xcr[k]] : 0u;
         uint64_t peers = match_lanes(c, valid, nbits);
         uint32_t below = bits_below(peers);
         uint32_t r = 0;
@@ -870,47 +904,216 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
   }
 }
 
+// Keys-only scatter.  Without a payload, equal keys are equal bit patterns, so
+// their order inside a child is immaterial and a chunk is regrouped with LDS
+// atomics instead of ballot ranks.  The next chunk's keys are loaded into
+// registers while the current one is classified, regrouped and written.
+constexpr uint32_t SCK_THREADS = 512;
+
+template <int KT, int KPT>
+AMS_DEV void sck_load(const typename Key<KT>::T *src, uint32_t cb, uint32_t hi,
+                      typename Key<KT>::T (&x)[KPT]) {
+#pragma unroll
+  for (int k = 0; k < KPT; ++k) {
+    const uint32_t p = cb + threadIdx.x + SCK_THREADS * k;
+    x[k] = p < hi ? src[p] : (typename Key<KT>::T)0;
+  }
+}
+
+template <int KT, int KPT>
+__global__ void __launch_bounds__(SCK_THREADS) k_scatter_keys(Ws w, Lev lv) {
+  typedef typename Key<KT>::T K;
+  constexpr uint32_t CHK = SCK_THREADS * KPT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint32_t CH = lv.CH;
+  K *sTree = (K *)smem_raw;                       // mmax
+  K *stK = sTree + lv.mmax;                       // CHK
+  uint16_t *stC = (uint16_t *)(stK + CHK);        // CHK
+  uint16_t *sI2C = stC + CHK;                     // HS
+  uint32_t *sBase = (uint32_t *)(sI2C + lv.HS);   // CH
+  uint32_t *sL = sBase + CH;                      // CH + 1
+  uint32_t *sCnt = sL + CH + 1;                   // CH
+  uint32_t *sTmp = sCnt + CH;                     // SCK_THREADS
+  uint8_t *sCd = (uint8_t *)(sTmp + SCK_THREADS); // CH
+  const uint32_t tid = threadIdx.x;
+  const uint32_t P = w.ctr->P;
+  ItemRange ir = xcd_items(w.ctr->ntile);
+  uint32_t cur = 0xFFFFFFFFu, logm = 0, nch = 0;
+  bool eq = false;
+  const K *gSpl = nullptr;
+  for (uint32_t g = ir.first; g < ir.end; g += ir.step) {
+    const uint32_t i = find_owner(w.tileStart, P, g);
+    const uint32_t t = g - w.tileStart[i];
+    const Seg s = w.act[lv.level][i];
+    const Root R = w.roots[s.root];
+    const uint32_t buf = seg_buf(s.meta);
+    const K *src = kptr<K>(w, R, buf) + s.off;
+    const bool enc = buf == BUF_IN;
+    const uint32_t lo = t * lv.TC;
+    const uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
+    K xa[KPT];
+    sck_load<KT, KPT>(src, lo, hi, xa);  // in flight while the tables load
+    if (i != cur) {
+      __syncthreads();
+      logm = meta_logm(s.meta);
+      const uint32_t m = 1u << logm;
+      const K *gt = (const K *)w.tree + (size_t)i * lv.mmax;
+      for (uint32_t j = tid + 1; j < m; j += SCK_THREADS) sTree[j] = gt[j];
+      eq = w.eqOn[i] != 0;
+      nch = w.nch[i];
+      const uint32_t NB = eq ? 2 * m - 1 : m;
+      const uint16_t *gi = w.i2c + (size_t)i * lv.HS;
+      for (uint32_t j = tid; j < NB; j += SCK_THREADS) sI2C[j] = gi[j];
+      const uint8_t *gd = w.cdst + (size_t)i * CH;
+      for (uint32_t c = tid; c < nch; c += SCK_THREADS) sCd[c] = gd[c];
+      gSpl = (const K *)w.spl + (size_t)i * lv.mmax;
+      cur = i;
+    }
+    for (uint32_t c = tid; c < nch; c += SCK_THREADS) sBase[c] = w.tileOff[(size_t)g * CH + c];
+    for (uint32_t cb = lo; cb < hi; cb += CHK) {
+      K xb[KPT];
+      if (cb + CHK < hi) sck_load<KT, KPT>(src, cb + CHK, hi, xb);
+      for (uint32_t c = tid; c < nch; c += SCK_THREADS) sCnt[c] = 0;
+      __syncthreads();
+      if (enc) {
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) xa[k] = Key<KT>::enc(xa[k]);
+      }
+      uint32_t xcs[KPT];  // child << 16 | slot
+      classify_batch<K, KPT>(xa, xcs, sTree, gSpl, logm, eq);
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const uint32_t p = cb + tid + SCK_THREADS * k;
+        uint32_t c = 0, slot = 0;
+        if (p < hi) {
+          c = sI2C[xcs[k]];
+          slot = atomicAdd(&sCnt[c], 1u);
+        }
+        xcs[k] = (c << 16) | slot;
+      }
+      __syncthreads();
+      for (uint32_t c = tid; c < nch; c += SCK_THREADS) sL[c] = sCnt[c];
+      __syncthreads();
+      block_exscan<SCK_THREADS>(sL, nch, sTmp);
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const uint32_t p = cb + tid + SCK_THREADS * k;
+        if (p < hi) {
+          const uint32_t c = xcs[k] >> 16;
+          const uint32_t q = sL[c] + (xcs[k] & 0xFFFFu);
+          stK[q] = xa[k];
+          stC[q] = (uint16_t)c;
+        }
+      }
+      __syncthreads();
+      const uint32_t cnt = hi - cb < CHK ? hi - cb : CHK;
+      for (uint32_t q = tid; q < cnt; q += SCK_THREADS) {
+        const uint32_t c = stC[q];
+        const uint32_t rel = sBase[c] + (q - sL[c]);
+        if (rel >= s.size) {  // defensive: never write outside the subproblem
+          atomicOr(&w.ctr->overflow, 16u);
+          continue;
+        }
+        const uint32_t cd = sCd[c];
+        K x = stK[q];
+        if (cd >> 4) x = Key<KT>::dec(x);
+        kptr<K>(w, R, cd & 15u)[s.off + rel] = x;
+      }
+      __syncthreads();
+      for (uint32_t c = tid; c < nch; c += SCK_THREADS) sBase[c] += sCnt[c];
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) xa[k] = xb[k];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Base case (Section 4.2 all-pairs ranking; Section 6 base case).
 // ---------------------------------------------------------------------------
 constexpr uint32_t FIN_KPT = CMAX / FIN_THREADS;  // 16 keys per thread
 constexpr uint32_t LEAF_STREAM = 0xFFu;
 
-// LDS of one base-case workgroup.  B holds the keys regrouped by bucket; the
-// sample, its sorted blocks and the splitter tree live inside B until the
-// keys are staged there.  Keys-only fits in 80 KiB (two workgroups per CU).
+// LDS of one base-case workgroup.  B holds the keys regrouped by bucket plus
+// FIN_PAD slots that receive the largest key value as sentinels; the sample,
+// its sorted blocks and the splitter tree live inside B until the keys are
+// staged there.  Keys-only fits in 80 KiB (two workgroups per CU).
+constexpr uint32_t FIN_PAD = 256;
+
 template <typename K> struct FinSmem {
-  K *B;             // C keys
+  K *B;             // C + FIN_PAD keys
   uint32_t *vB;     // C payloads (pairs only)
   uint8_t *bid;     // C: bucket index b of each staged key (equality bit recomputed)
-  uint32_t *bstart; // 2*FMAX + 4 bucket starts
+  uint32_t *bstart; // 2*FMAX + 4 bucket starts; bstart[2*FMAX+2] holds the largest bucket
   uint32_t *cnt;    // bucket counters (keys-only) or 8 per-wave rows (pairs)
   uint32_t *tmp;    // FIN_THREADS words of scan scratch (aliases cnt for keys-only)
+  uint32_t *bm;     // C bits: placed positions (keys-only; aliases cnt)
   K *srt;           // FMAX sorted samples; srt[1..f-1] are the splitters
-  K *smp, *blk, *tree;  // overlays inside B: samples, block-sorted samples, tree
+  K *smp, *blk, *tree;  // overlays in the bid region: samples, block-sorted samples, tree
 };
 
 template <typename K, bool PAY> AMS_HD size_t fin_cnt_words() { return PAY ? 8 * 2 * FMAX : 2 * FMAX; }
 
+template <typename K> AMS_HD uint32_t fin_bid_bytes(uint32_t C) {
+  const uint32_t b = (C + 15) & ~15u, o = 3 * FMAX * (uint32_t)sizeof(K);
+  return b > o ? b : o;
+}
+
 template <typename K, bool PAY> AMS_DEV FinSmem<K> fin_smem(unsigned char *base, uint32_t C) {
   FinSmem<K> f;
   f.B = (K *)base;
-  f.vB = (uint32_t *)(f.B + C);
+  f.vB = (uint32_t *)(f.B + C + FIN_PAD);
   f.bid = (uint8_t *)(f.vB + (PAY ? C : 0));
-  f.bstart = (uint32_t *)(f.bid + ((C + 15) & ~15u));
+  f.bstart = (uint32_t *)(f.bid + fin_bid_bytes<K>(C));
   f.cnt = f.bstart + 2 * FMAX + 4;
   f.tmp = PAY ? f.cnt + fin_cnt_words<K, PAY>() : f.cnt;
+  f.bm = f.cnt;
   f.srt = (K *)(f.tmp + (PAY ? FIN_THREADS : fin_cnt_words<K, PAY>()));
-  f.smp = f.B;
-  f.blk = f.B + FMAX;
-  f.tree = f.B + 2 * FMAX;
+  f.smp = (K *)f.bid;  // sample overlays live in the bucket-id region until staging
+  f.blk = f.smp + FMAX;
+  f.tree = f.smp + 2 * FMAX;
   return f;
 }
 
 template <typename K, bool PAY> __host__ inline size_t fin_smem_bytes(uint32_t C) {
-  return (size_t)C * sizeof(K) + (PAY ? (size_t)C * 4 : 0) + ((C + 15) & ~15u) +
+  return (size_t)(C + FIN_PAD) * sizeof(K) + (PAY ? (size_t)C * 4 : 0) + fin_bid_bytes<K>(C) +
          (2 * FMAX + 4) * 4 + fin_cnt_words<K, PAY>() * 4 + (PAY ? FIN_THREADS * 4 : 0) +
          FMAX * sizeof(K);
+}
+
+// Largest leaf the base case takes for a key width / payload: keys-only
+// stays within 80 KiB of LDS so that two workgroups share a CU.
+__host__ inline uint32_t fin_capacity(uint32_t kw, bool pay) {
+  uint32_t C = CMAX;
+  while (C > 1024) {
+    size_t b = kw == 8 ? (pay ? fin_smem_bytes<uint64_t, true>(C) : fin_smem_bytes<uint64_t, false>(C))
+                       : (pay ? fin_smem_bytes<uint32_t, true>(C) : fin_smem_bytes<uint32_t, false>(C));
+    // keep 1 KiB for the kernel's static LDS (barrier reductions)
+    if (b <= (pay ? 163840u : 81920u) - 1024u) break;
+    C -= 16;
+  }
+  return C;
+}
+
+// classify FIN_KPT keys in two batches of half the width (register pressure)
+template <typename K>
+AMS_DEV void classify_halves(K (&x)[FIN_KPT], uint32_t (&id)[FIN_KPT], const K *tree, const K *spl,
+                             uint32_t logf, bool eq, uint32_t s) {
+  constexpr int H = FIN_KPT / 2;
+  K xa[H];
+  uint32_t ia[H];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h * H * FIN_THREADS >= s) {  // uniform: no key in this half of the slots
+#pragma unroll
+      for (int u = 0; u < H; ++u) id[h * H + u] = 0;
+      continue;
+    }
+#pragma unroll
+    for (int u = 0; u < H; ++u) xa[u] = x[h * H + u];
+    classify_batch<K, H>(xa, ia, tree, spl, logf, eq);
+#pragma unroll
+    for (int u = 0; u < H; ++u) id[h * H + u] = ia[u];
+  }
 }
 
 // Sort s <= C keys from src into dst inside one workgroup.
@@ -920,13 +1123,17 @@ template <typename K, bool PAY> __host__ inline size_t fin_smem_bytes(uint32_t C
 //  2. Every key is classified and placed in LDS by bucket (keys-only: LDS
 //     atomics, order inside a bucket arbitrary since equal keys are equal
 //     bits; pairs: ballot ranks, input order kept).
-//  3. Every bucket is ordered by comparing all its pairs:
-//     rank(x_q) = #{j : x_j < x_q} + #{j < q : x_j = x_q}.
+//  3. Every bucket is ordered by comparing all its pairs (Section 4.2):
+//     pairs: rank(x_q) = #{j : x_j < x_q} + #{j < q : x_j = x_q};
+//     keys-only: rank(x_q) = #{j : x_j < x_q}; equal keys then share a rank,
+//     and the positions they leave empty are filled with the same bits.
+//     Keys after a bucket are larger (buckets follow key order) and the pad
+//     holds the largest value, so a scan may run past its bucket unmasked.
 template <int KT, bool PAY>
 AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
                       const typename Key<KT>::T *src, const uint32_t *vsrc, bool enc_in,
                       typename Key<KT>::T *dst, uint32_t *vdst, bool dec_out, uint32_t s,
-                      uint32_t cutoff, uint64_t st) {
+                      uint32_t C, uint32_t cutoff, uint64_t st) {
   typedef typename Key<KT>::T K;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t f = 1;
@@ -938,12 +1145,29 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   }
   const uint32_t logf = ilog2c(f);
   const K *spl = sm.srt + 1;  // spl[b] = splitter just above bucket b
+  K xk[FIN_KPT];
+  uint32_t xv[FIN_KPT];
+  uint32_t xir[FIN_KPT];  // id << 16 | slot
+  // keys into registers; pairs: waves own contiguous ranges (stable split)
+  const uint32_t nsteps = (s + 63) / 64, spw = (nsteps + 7) / 8;
+#pragma unroll
+  for (uint32_t k = 0; k < FIN_KPT; ++k) {
+    const uint32_t p = PAY ? (wave * spw + k) * 64 + lane : tid + FIN_THREADS * k;
+    const bool valid = PAY ? (k < spw && p < s) : p < s;
+    K x = valid ? src[p] : (K)0;
+    xk[k] = enc_in ? Key<KT>::enc(x) : x;
+    if (PAY) xv[k] = valid ? vsrc[p] : 0u;
+  }
   bool eq = false;
   if (f > 1) {
-    if (tid < f) {
-      K x = src[draw_pos(st, tid, s)];
-      sm.smp[tid] = enc_in ? Key<KT>::enc(x) : x;
+    // stage the keys in input order and draw the sample from LDS
+#pragma unroll
+    for (uint32_t k = 0; k < FIN_KPT; ++k) {
+      const uint32_t p = PAY ? (wave * spw + k) * 64 + lane : tid + FIN_THREADS * k;
+      if (PAY ? (k < spw && p < s) : p < s) sm.B[p] = xk[k];
     }
+    __syncthreads();
+    if (tid < f) sm.smp[tid] = sm.B[draw_pos(st, tid, s)];
     __syncthreads();
     const uint32_t bsz = f < 64 ? f : 64, nbk = (f + 63) / 64;
     if (tid < f) {
@@ -974,11 +1198,12 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       dup = tid + 1 < f && sm.srt[tid] == sm.srt[tid + 1];
     }
     eq = __syncthreads_or(dup ? 1 : 0) != 0;
+    classify_halves<K>(xk, xir, sm.tree, spl, logf, eq, s);
+  } else {
+#pragma unroll
+    for (uint32_t k = 0; k < FIN_KPT; ++k) xir[k] = 0;
   }
   const uint32_t NB = f == 1 ? 1 : (eq ? 2 * f - 1 : f);
-  K xk[FIN_KPT];
-  uint32_t xv[FIN_KPT];
-  uint32_t xir[FIN_KPT];  // id << 16 | slot
   if (!PAY) {
     // ---- keys only: unstable split with LDS atomics ----
     if (tid < NB) sm.cnt[tid] = 0;
@@ -986,27 +1211,14 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
 #pragma unroll
     for (uint32_t k = 0; k < FIN_KPT; ++k) {
       const uint32_t p = tid + FIN_THREADS * k;
-      const bool valid = p < s;
-      K x = valid ? src[p] : (K)0;
-      if (enc_in) x = Key<KT>::enc(x);
-      xk[k] = x;
-    }
-#pragma unroll
-    for (uint32_t k = 0; k < FIN_KPT; ++k) {
-      const uint32_t p = tid + FIN_THREADS * k;
-      uint32_t id = 0, slot = 0;
-      if (p < s) {
-        id = f > 1 ? classify_id(xk[k], sm.tree, spl, logf, eq) : 0u;
-        slot = atomicAdd(&sm.cnt[id], 1u);
-      }
-      xir[k] = (id << 16) | slot;
+      uint32_t slot = 0;
+      if (p < s) slot = atomicAdd(&sm.cnt[xir[k]], 1u);
+      xir[k] = (xir[k] << 16) | slot;
     }
     __syncthreads();
     if (tid < NB) sm.bstart[tid] = sm.cnt[tid];
     __syncthreads();
     block_exscan<FIN_THREADS>(sm.bstart, NB, sm.tmp);
-    if (tid == 0) sm.bstart[NB] = s;
-    __syncthreads();
 #pragma unroll
     for (uint32_t k = 0; k < FIN_KPT; ++k) {
       const uint32_t p = tid + FIN_THREADS * k;
@@ -1017,20 +1229,17 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         sm.bid[q] = (uint8_t)(eq ? id >> 1 : id);
       }
     }
+    for (uint32_t w32 = tid; w32 < (C + 31) / 32; w32 += FIN_THREADS) sm.bm[w32] = 0;
   } else {
-    // ---- pairs: stable split, waves own contiguous ranges, ballot ranks ----
+    // ---- pairs: stable split, ballot ranks inside each wave's range ----
     const uint32_t nbits = ilog2c(NB);
     for (uint32_t q = tid; q < 8 * NB; q += FIN_THREADS) sm.cnt[q] = 0;
     __syncthreads();
-    const uint32_t nsteps = (s + 63) / 64, spw = (nsteps + 7) / 8;
 #pragma unroll
     for (uint32_t k = 0; k < FIN_KPT; ++k) {
       const uint32_t p = (wave * spw + k) * 64 + lane;
       const bool valid = k < spw && p < s;
-      K x = valid ? src[p] : (K)0;
-      if (enc_in) x = Key<KT>::enc(x);
-      uint32_t v = valid ? vsrc[p] : 0u;
-      uint32_t id = (valid && f > 1) ? classify_id(x, sm.tree, spl, logf, eq) : 0u;
+      const uint32_t id = valid ? xir[k] : 0u;
       uint64_t peers = match_lanes(id, valid, nbits);
       uint32_t below = bits_below(peers);
       uint32_t r = 0;
@@ -1039,8 +1248,6 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         r = *c + below;
         if (below == 0) *c = r + (uint32_t)__popcll(peers);
       }
-      xk[k] = x;
-      xv[k] = v;
       xir[k] = (id << 16) | r;
     }
     __syncthreads();
@@ -1051,7 +1258,6 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     }
     __syncthreads();
     block_exscan<FIN_THREADS>(sm.bstart, NB, sm.tmp);
-    if (tid == 0) sm.bstart[NB] = s;
     for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
       uint32_t run = sm.bstart[id];
       for (uint32_t ww = 0; ww < 8; ++ww) {
@@ -1073,52 +1279,116 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       }
     }
   }
+  // largest bucket, for the sentinel pad
+  uint32_t *shMax = sm.bstart + 2 * FMAX + 2;
+  if (tid == 0) {
+    sm.bstart[NB] = s;
+    *shMax = 0;
+  }
   __syncthreads();
-  // ---- all-pairs rank inside every bucket; waves run a common trip count ----
-  uint32_t fpos[FIN_KPT];
+  if (tid < NB) atomicMax(shMax, sm.bstart[tid + 1] - sm.bstart[tid]);
+  __syncthreads();
+  const uint32_t Lb = *shMax;
+  const bool padded = s + Lb + 4 <= C + FIN_PAD;
+  if (padded)
+    for (uint32_t q = s + tid; q < s + Lb + 4; q += FIN_THREADS) sm.B[q] = (K)~(K)0;
+  __syncthreads();
+  // ---- all-pairs rank inside every bucket; two slots per pass, waves run a
+  // common trip count.  B is not modified while ranking, so every key goes
+  // straight to its final position in dst once its rank is known.
 #pragma unroll
-  for (uint32_t k = 0; k < FIN_KPT; ++k) {
-    const uint32_t q = tid + FIN_THREADS * k;
-    const bool valid = q < s;
-    const uint32_t qs = valid ? q : 0u;
-    const K x = sm.B[qs];
-    const uint32_t b = sm.bid[qs];
-    const uint32_t id = eq ? 2 * b + ((b + 1 < f && x == spl[b]) ? 1u : 0u) : b;
-    const uint32_t bs = valid ? sm.bstart[id] : 0u;
-    const uint32_t be = valid ? sm.bstart[id + 1] : 0u;
-    const bool isEq = eq && (id & 1u);  // equal keys, already in place order
-    const uint32_t len = (valid && !isEq) ? be - bs : 0u;
-    const uint32_t ml = wave_max(len);
-    uint32_t rk = 0;
-    for (uint32_t d = 0; d < ml; d += 4) {
+  for (uint32_t k = 0; k < FIN_KPT; k += 2) {
+    if (FIN_THREADS * k >= s) continue;  // uniform: slot pair holds no key
+    uint32_t q[2], bs[2], len[2], rk[2] = {0, 0}, v[2] = {0, 0};
+    K x[2];
+    bool isEq[2];
 #pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) {
-        const uint32_t dd = d + u;
-        const bool in = dd < len;
-        const uint32_t j = in ? bs + dd : qs;
-        const K y = sm.B[j];
-        rk += (uint32_t)in & ((uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(j < q)));
+    for (int h = 0; h < 2; ++h) {
+      q[h] = tid + FIN_THREADS * (k + h);
+      const bool valid = q[h] < s;
+      const uint32_t qs = valid ? q[h] : 0u;
+      x[h] = sm.B[qs];
+      const uint32_t b = sm.bid[qs];
+      const uint32_t id = eq ? 2 * b + ((b + 1 < f && x[h] == spl[b]) ? 1u : 0u) : b;
+      bs[h] = valid ? sm.bstart[id] : 0u;
+      const uint32_t be = valid ? sm.bstart[id + 1] : 0u;
+      isEq[h] = eq && (id & 1u);  // equal keys: any arrangement is final
+      len[h] = (valid && !isEq[h]) ? be - bs[h] : 0u;
+      if (PAY) v[h] = sm.vB[qs];
+    }
+    const uint32_t ml = wave_max(len[0] > len[1] ? len[0] : len[1]);
+    if (padded) {
+      const K *a0 = sm.B + bs[0];
+      const K *a1 = sm.B + bs[1];
+      if (!PAY) {
+        for (uint32_t d = 0; d < ml; d += 4) {
+          K y0[4], y1[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            y0[u] = a0[d + u];
+            y1[u] = a1[d + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            rk[0] += (uint32_t)(y0[u] < x[0]);
+            rk[1] += (uint32_t)(y1[u] < x[1]);
+          }
+        }
+      } else {
+        const uint32_t qb0 = q[0] - bs[0], qb1 = q[1] - bs[1];  // j < q  <=>  d + u < qb
+        for (uint32_t d = 0; d < ml; d += 4) {
+          K y0[4], y1[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            y0[u] = a0[d + u];
+            y1[u] = a1[d + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            rk[0] += (uint32_t)(y0[u] < x[0]) | ((uint32_t)(y0[u] == x[0]) & (uint32_t)(d + u < qb0));
+            rk[1] += (uint32_t)(y1[u] < x[1]) | ((uint32_t)(y1[u] == x[1]) & (uint32_t)(d + u < qb1));
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t mh = wave_max(len[h]);
+        const uint32_t qs = q[h] < s ? q[h] : 0u;
+        for (uint32_t d = 0; d < mh; d += 4) {
+          K y[4];
+          uint32_t jj[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            jj[u] = d + u < len[h] ? bs[h] + d + u : qs;
+            y[u] = sm.B[jj[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            rk[h] += (uint32_t)(d + u < len[h]) &
+                     ((uint32_t)(y[u] < x[h]) | ((uint32_t)(y[u] == x[h]) & (uint32_t)(jj[u] < q[h])));
+        }
       }
     }
-    if (isEq) rk = q - bs;
-    fpos[k] = bs + rk;
-    xk[k] = x;
-    if (PAY) xv[k] = sm.vB[qs];
-  }
-  __syncthreads();
 #pragma unroll
-  for (uint32_t k = 0; k < FIN_KPT; ++k) {
-    const uint32_t q = tid + FIN_THREADS * k;
-    if (q < s) {
-      sm.B[fpos[k]] = xk[k];
-      if (PAY) sm.vB[fpos[k]] = xv[k];
+    for (int h = 0; h < 2; ++h) {
+      if (q[h] >= s) continue;
+      uint32_t pos = isEq[h] ? q[h] : bs[h] + rk[h];
+      const K out = dec_out ? Key<KT>::dec(x[h]) : x[h];
+      if (!PAY && !isEq[h] && !padded) {
+        // masked path ranks with the position tie-break: ranks are unique
+      } else if (!PAY && !isEq[h]) {
+        // keys sharing a rank are equal bits: the first claims the rank,
+        // the others claim the empty positions right after it
+        uint32_t old = atomicOr(&sm.bm[pos >> 5], 1u << (pos & 31u));
+        while (old & (1u << (pos & 31u))) {
+          ++pos;
+          old = atomicOr(&sm.bm[pos >> 5], 1u << (pos & 31u));
+        }
+      }
+      dst[pos] = out;
+      if (PAY) vdst[pos] = v[h];
     }
-  }
-  __syncthreads();
-  for (uint32_t q = tid; q < s; q += FIN_THREADS) {
-    K x = sm.B[q];
-    dst[q] = dec_out ? Key<KT>::dec(x) : x;
-    if (PAY) vdst[q] = sm.vB[q];
   }
   __syncthreads();
 }
@@ -1190,7 +1460,7 @@ __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint3
     }
     const uint64_t st = stream_state(seed, LEAF_STREAM, L.root, L.off);
     if (kind == LEAF_REG) {
-      lds_sort<KT, PAY>(sm, src, vsrc, buf == BUF_IN, dst, vdst, true, L.size, cutoff, st);
+      lds_sort<KT, PAY>(sm, src, vsrc, buf == BUF_IN, dst, vdst, true, L.size, C, cutoff, st);
       continue;
     }
     // Oversized leaf (a group larger than LDS after the planned levels):
@@ -1207,7 +1477,7 @@ __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint3
     for (uint32_t r = 0; r < runs; ++r) {
       uint32_t o = r * C, sz = n - o < C ? n - o : C;
       lds_sort<KT, PAY>(sm, src + o, PAY ? vsrc + o : nullptr, buf == BUF_IN, bufK[curb] + o,
-                        PAY ? bufV[curb] + o : nullptr, false, sz, cutoff,
+                        PAY ? bufV[curb] + o : nullptr, false, sz, C, cutoff,
                         stream_state(seed, LEAF_STREAM, L.root, L.off + o));
     }
     for (uint32_t pz = 0; pz < passes; ++pz) {
@@ -1343,12 +1613,12 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
   }
   pl.ntotal = total;
   pl.maxroot = mx;
-  uint32_t C = CMAX;
+  uint32_t C = fin_capacity(pl.kw, pay);
   if (p && p->leaf_capacity) {
     // the base case needs room for its sample overlays (3 * FMAX keys); step
     // entry points that never run the base case may go lower
     const uint32_t lo = (p->flags & FLAG_NO_BASE_CASE) ? 64 : 1024;
-    C = std::max<uint32_t>(lo, std::min<uint32_t>(p->leaf_capacity, CMAX) & ~15u);
+    C = std::max<uint32_t>(lo, std::min<uint32_t>(p->leaf_capacity, C) & ~15u);
   }
   pl.C = C;
   uint64_t keysBig = 0;
@@ -1463,7 +1733,7 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
   pl.o_eq = take(any ? capAct : 0);
   pl.o_hist = take(any ? (size_t)capTile * maxHS * 4 : 0);
   pl.o_blkHist = take(any ? (size_t)capBlk * maxHS * 4 : 0);
-  pl.o_blkOff = take(any ? (size_t)capBlk * maxCH * 4 : 0);
+  pl.o_totals = take(any ? (size_t)capAct * maxHS * 4 : 0);
   pl.o_tileOff = take(any ? (size_t)capTile * maxCH * 4 : 0);
   pl.o_i2c = take(any ? (size_t)capAct * maxHS * 2 : 0);
   pl.o_cfirst = take(any ? (size_t)capAct * (maxCH + 1) * 2 : 0);
@@ -1498,7 +1768,7 @@ static Ws carve(const Plan &pl, char *base) {
   w.eqOn = (uint8_t *)(base + pl.o_eq);
   w.hist = (uint32_t *)(base + pl.o_hist);
   w.blkHist = (uint32_t *)(base + pl.o_blkHist);
-  w.blkOff = (uint32_t *)(base + pl.o_blkOff);
+  w.totals = (uint32_t *)(base + pl.o_totals);
   w.tileOff = (uint32_t *)(base + pl.o_tileOff);
   w.i2c = (uint16_t *)(base + pl.o_i2c);
   w.cfirst = (uint16_t *)(base + pl.o_cfirst);
@@ -1593,15 +1863,20 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
       hipLaunchKernelGGL(k_sample_rank<KT>, dim3(grid_for((uint64_t)ls.P * ng, 1024)), dim3(256),
                          lds, s, w, lv);
     }
-    size_t ldsC = 2 * (size_t)ls.mmax * sizeof(K) + 4 * (size_t)ls.HS * 4;
+    size_t ldsC = 2 * (size_t)ls.mmax * sizeof(K) + (size_t)ls.HS * 4;
     allow_lds(k_count<KT>, ldsC);
     {
       TraceScope ts("count", l, s);
-      hipLaunchKernelGGL(k_count<KT>, dim3(grid_for(ls.tiles, 1024)), dim3(256), ldsC, s, w, lv);
+      hipLaunchKernelGGL(k_count<KT>, dim3(grid_for(ls.tiles, 2048)), dim3(256), ldsC, s, w, lv);
     }
     {
       TraceScope ts("block_reduce", l, s);
       hipLaunchKernelGGL(k_block_reduce, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
+    }
+    {
+      TraceScope ts("block_scan", l, s);
+      hipLaunchKernelGGL(k_block_scan, dim3(grid_for((uint64_t)ls.P * ((ls.HS + 255) / 256), 1024)),
+                         dim3(256), 0, s, w, lv);
     }
     size_t ldsP = (size_t)ls.HS * 4 * 2 + (size_t)(ls.CH + 1) * 4 * 2 + 256 * 4 + 16 * 4 +
                   (size_t)(ls.CH + 1) * 2 * 2 + ls.HS + ls.CH + 64;
@@ -1614,16 +1889,25 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
       TraceScope ts("tile_scan", l, s);
       hipLaunchKernelGGL(k_tile_scan, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
     }
-    constexpr int KPT = PAY ? 8 : 16;
-    constexpr uint32_t CHK = 256 * KPT;
-    size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + (PAY ? CHK * 4 : 0) + CHK * 2 +
-                  (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + 4 + (size_t)ls.CH * 16 + 256 * 4 +
-                  ls.CH + 64;
-    allow_lds(k_scatter<KT, PAY, KPT>, ldsS);
-    {
+    if (PAY) {
+      constexpr int KPT = 8;
+      constexpr uint32_t CHK = 256 * KPT;
+      size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + CHK * 4 + CHK * 2 +
+                    (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + 4 + (size_t)ls.CH * 16 + 256 * 4 +
+                    ls.CH + 64;
+      allow_lds(k_scatter<KT, true, KPT>, ldsS);
       TraceScope ts("scatter", l, s);
-      hipLaunchKernelGGL((k_scatter<KT, PAY, KPT>), dim3(grid_for(ls.tiles, 512)), dim3(256),
+      hipLaunchKernelGGL((k_scatter<KT, true, KPT>), dim3(grid_for(ls.tiles, 512)), dim3(256),
                          ldsS, s, w, lv);
+    } else {
+      constexpr int KPT = 8;
+      constexpr uint32_t CHK = SCK_THREADS * KPT;
+      size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + CHK * 2 + (size_t)ls.HS * 2 +
+                    (size_t)ls.CH * 4 * 3 + 4 + SCK_THREADS * 4 + ls.CH + 64;
+      allow_lds(k_scatter_keys<KT, KPT>, ldsS);
+      TraceScope ts("scatter", l, s);
+      hipLaunchKernelGGL((k_scatter_keys<KT, KPT>), dim3(grid_for(ls.tiles, 512)),
+                         dim3(SCK_THREADS), ldsS, s, w, lv);
     }
   }
   if (!dbg_hist) {
