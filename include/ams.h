@@ -76,6 +76,9 @@ typedef struct {
 } ams_params;
 
 #define AMS_FLAG_EQ_ALWAYS 1u /* equality buckets on for every subproblem */
+#define AMS_FLAG_STABLE_PARTITION 2u /* keys-only: partition levels keep input order inside
+                                        every child (pairs always do); the sorted output is
+                                        the same either way */
 
 /* Bytes of device workspace a call with these arguments needs.  Returns 0 on
  * invalid arguments.  ams_sort_* accept d_ws = NULL, in which case they

@@ -484,17 +484,27 @@ struct Greedy {
   uint32_t maxG, zmin;
 };
 
+// wgt is 16-byte aligned and padded with zeros to a multiple of 8 entries;
+// eight weights are fetched per step so the scan is not bound by LDS latency
+// (zero weights never open a group).
 AMS_DEV Greedy greedy_scan(const uint32_t *wgt, uint32_t nb, uint32_t L, uint32_t r) {
   uint32_t cur = 0, groups = 1, maxG = 0, zmin = 0xFFFFFFFFu;
-  for (uint32_t j = 0; j < nb; ++j) {
-    uint32_t wj = wgt[j];
-    if (cur + wj > L) {
-      zmin = min(zmin, cur + wj);
-      maxG = max(maxG, cur);
-      ++groups;
-      cur = wj;
-    } else {
-      cur += wj;
+  const uint4 *w4 = (const uint4 *)wgt;
+  const uint32_t n8 = (nb + 7) / 8;
+  for (uint32_t j = 0; j < n8; ++j) {
+    const uint4 a = w4[2 * j], b = w4[2 * j + 1];
+    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t t = cur + v[u];
+      if (t > L) {
+        zmin = min(zmin, t);
+        maxG = max(maxG, cur);
+        ++groups;
+        cur = v[u];
+      } else {
+        cur = t;
+      }
     }
   }
   maxG = max(maxG, cur);
@@ -570,7 +580,7 @@ AMS_DEV PackSmem pack_smem(unsigned char *base, uint32_t HS, uint32_t CH) {
   PackSmem p;
   p.tot = (uint32_t *)base;
   p.wgt = p.tot + HS;
-  p.sz = p.wgt + HS;
+  p.sz = p.wgt + HS + 8;  // weights are zero-padded to a multiple of 8
   p.start = p.sz + CH + 1;
   p.tmp = p.start + CH + 1;
   p.red = p.tmp + 256;
@@ -585,8 +595,19 @@ AMS_DEV PackSmem pack_smem(unsigned char *base, uint32_t HS, uint32_t CH) {
 // greedy groups under L, cut at final equality buckets; returns the count.
 AMS_DEV uint32_t build_children(const PackSmem &p, uint32_t NB, uint32_t L, uint32_t CH) {
   uint32_t cur = 0, pf = 0, psz = 0, nch = 0;
+  uint32_t wv[8], tv[8];
+  uint8_t fv[8];
   for (uint32_t j = 0; j < NB && nch + 2 < CH; ++j) {
-    uint32_t wj = p.wgt[j];
+    if ((j & 7u) == 0) {  // fetch the next eight ids ahead of the scan
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t jj = j + u < NB ? j + u : NB - 1;
+        wv[u] = p.wgt[jj];
+        tv[u] = p.tot[jj];
+        fv[u] = p.fin[jj];
+      }
+    }
+    const uint32_t wj = wv[j & 7u];
     if (cur + wj > L) {
       if (psz) {
         p.first[nch] = pf; p.end[nch] = j; p.sz[nch] = psz; p.kind[nch] = CHILD_REG; ++nch;
@@ -596,15 +617,15 @@ AMS_DEV uint32_t build_children(const PackSmem &p, uint32_t NB, uint32_t L, uint
       cur = 0;
     }
     cur += wj;
-    if (p.fin[j]) {
+    if (fv[j & 7u]) {
       if (psz) {
         p.first[nch] = pf; p.end[nch] = j; p.sz[nch] = psz; p.kind[nch] = CHILD_REG; ++nch;
       }
-      p.first[nch] = j; p.end[nch] = j + 1; p.sz[nch] = p.tot[j]; p.kind[nch] = CHILD_FINAL; ++nch;
+      p.first[nch] = j; p.end[nch] = j + 1; p.sz[nch] = tv[j & 7u]; p.kind[nch] = CHILD_FINAL; ++nch;
       pf = j + 1;
       psz = 0;
     } else {
-      psz += p.tot[j];
+      psz += tv[j & 7u];
     }
   }
   if (psz && nch < CH) {
@@ -631,10 +652,10 @@ __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
     __syncthreads();
     const uint32_t N = s.size;
     const uint32_t tfin = (N + r - 1) / r;
-    for (uint32_t id = tid; id < NB; id += 256) {
-      bool fin = eq && (id & 1u) && p.tot[id] >= tfin;
-      p.fin[id] = fin ? 1 : 0;
-      p.wgt[id] = fin ? 0u : p.tot[id];
+    for (uint32_t id = tid; id < ((NB + 7) & ~7u); id += 256) {
+      bool fin = id < NB && eq && (id & 1u) && p.tot[id] >= tfin;
+      if (id < NB) p.fin[id] = fin ? 1 : 0;
+      p.wgt[id] = (fin || id >= NB) ? 0u : p.tot[id];
     }
     __syncthreads();
     const uint32_t L = optimal_load<256>(p.wgt, NB, r, p.red);
@@ -714,7 +735,7 @@ __global__ void __launch_bounds__(256) k_pack_only(const uint32_t *wgt, uint32_t
   extern __shared__ __align__(16) unsigned char smem_raw[];
   uint32_t *sW = (uint32_t *)smem_raw;
   __shared__ uint32_t red[16];
-  for (uint32_t j = threadIdx.x; j < nb; j += 256) sW[j] = wgt[j];
+  for (uint32_t j = threadIdx.x; j < ((nb + 7) & ~7u); j += 256) sW[j] = j < nb ? wgt[j] : 0u;
   __syncthreads();
   uint32_t L = optimal_load<256>(sW, nb, r, red);
   if (threadIdx.x == 0) {
@@ -1878,7 +1899,7 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
       hipLaunchKernelGGL(k_block_scan, dim3(grid_for((uint64_t)ls.P * ((ls.HS + 255) / 256), 1024)),
                          dim3(256), 0, s, w, lv);
     }
-    size_t ldsP = (size_t)ls.HS * 4 * 2 + (size_t)(ls.CH + 1) * 4 * 2 + 256 * 4 + 16 * 4 +
+    size_t ldsP = (size_t)ls.HS * 4 * 2 + 32 + (size_t)(ls.CH + 1) * 4 * 2 + 256 * 4 + 16 * 4 +
                   (size_t)(ls.CH + 1) * 2 * 2 + ls.HS + ls.CH + 64;
     allow_lds(k_pack, ldsP);
     {
@@ -1889,7 +1910,16 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
       TraceScope ts("tile_scan", l, s);
       hipLaunchKernelGGL(k_tile_scan, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
     }
-    if (PAY) {
+    if (!PAY && (pl.flags & AMS_FLAG_STABLE_PARTITION)) {
+      constexpr int KPT = 16;
+      constexpr uint32_t CHK = 256 * KPT;
+      size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + CHK * 2 + (size_t)ls.HS * 2 +
+                    (size_t)ls.CH * 4 * 3 + 4 + (size_t)ls.CH * 16 + 256 * 4 + ls.CH + 64;
+      allow_lds(k_scatter<KT, false, KPT>, ldsS);
+      TraceScope ts("scatter", l, s);
+      hipLaunchKernelGGL((k_scatter<KT, false, KPT>), dim3(grid_for(ls.tiles, 512)), dim3(256),
+                         ldsS, s, w, lv);
+    } else if (PAY) {
       constexpr int KPT = 8;
       constexpr uint32_t CHK = 256 * KPT;
       size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + CHK * 4 + CHK * 2 +
@@ -1947,7 +1977,7 @@ ams_status run_plan(const Plan &pl, void *ws, const RootSource &src, hipStream_t
 // Step entry point helpers -------------------------------------------------
 ams_status run_pack_only(const uint32_t *d_w, uint32_t nb, uint32_t r, uint32_t *d_out,
                          hipStream_t s) {
-  size_t lds = (size_t)nb * 4 + 64;
+  size_t lds = (size_t)((nb + 7) & ~7u) * 4 + 64;
   allow_lds(k_pack_only, lds);
   hipLaunchKernelGGL(k_pack_only, dim3(1), dim3(256), lds, s, d_w, nb, r, d_out);
   hipError_t e = hipGetLastError();

@@ -1,0 +1,128 @@
+"""GPU parity of the batched sort, of deep and forced level plans, and of the
+oversized-group fallback."""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import gen, log, to_dev, to_host
+from paper_1410_6754_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+U32, U64, F32 = W.KEY_U32, W.KEY_U64, W.KEY_F32
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1410_6754_amd import api as A
+    return A
+
+
+def _segments(rng, count, lo_exp, hi_exp):
+    sizes = W.batch_sizes(count, rng, lo_exp, hi_exp)
+    sizes[::17] = 0
+    sizes[1::19] = 1
+    return sizes
+
+
+@pytest.mark.parametrize("kt", [U64, U32, F32])
+def test_batch_keys_match_oracle_per_segment(api, kt):
+    rng = np.random.default_rng(31 + kt)
+    sizes = _segments(rng, 300, 4, 17)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    keys = gen(kt, int(offs[-1]), "uniform", 40 + kt)
+    log("batch kt=%d segments=%d total=%d" % (kt, sizes.size, int(offs[-1])))
+    out = to_host(api.sort_batch(to_dev(keys), offs))
+    for i in range(sizes.size):
+        a, b = int(offs[i]), int(offs[i + 1])
+        want, _ = oracle.oracle_sort(kt, keys[a:b])
+        assert np.array_equal(out[a:b].view(np.uint8), want.view(np.uint8)), i
+
+
+def test_batch_pairs_and_alone_equals_in_batch(api):
+    rng = np.random.default_rng(33)
+    sizes = _segments(rng, 120, 6, 18)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    n = int(offs[-1])
+    keys = gen(U64, n, "few", 41)
+    vals = np.arange(n, dtype=np.uint32)
+    dk, dv = to_dev(keys), to_dev(vals)
+    ok, ov = api.sort_batch(dk, offs, vals=dv)
+    ok, ov = to_host(ok), to_host(ov)
+    for i in range(sizes.size):
+        a, b = int(offs[i]), int(offs[i + 1])
+        wk, wv = oracle.oracle_sort(U64, keys[a:b], vals[a:b])
+        assert np.array_equal(ok[a:b], wk) and np.array_equal(ov[a:b], wv), i
+        if b - a > 0 and i % 10 == 0:
+            ak, av = api.sort_pairs(to_dev(keys[a:b].copy()), to_dev(vals[a:b].copy()))
+            assert np.array_equal(to_host(ak), ok[a:b]) and np.array_equal(to_host(av), ov[a:b])
+
+
+def test_batch_in_place_and_device_offsets(api):
+    import torch
+    rng = np.random.default_rng(35)
+    sizes = _segments(rng, 64, 8, 16)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    keys = gen(U32, int(offs[-1]), "uniform", 43)
+    d = to_dev(keys)
+    api.sort_batch(d, offs, out_keys=d, d_offsets=torch.from_numpy(offs).cuda())
+    out = to_host(d)
+    for i in range(sizes.size):
+        a, b = int(offs[i]), int(offs[i + 1])
+        want, _ = oracle.oracle_sort(U32, keys[a:b])
+        assert np.array_equal(out[a:b], want)
+
+
+@pytest.mark.parametrize("levels,k,b", [(3, 4, 2), (2, 16, 4), (1, 1024, 2), (3, 64, 1)])
+def test_forced_level_plans(api, levels, k, b):
+    n = 300000
+    keys = gen(U64, n, "uniform", 50 + levels * k)
+    p = api.make_params(levels=levels, k=k, overpartition_b=b, samples_per_bucket=4)
+    log("levels=%d k=%d b=%d" % (levels, k, b))
+    out = to_host(api.sort_keys(to_dev(keys), params=p))
+    want, _ = oracle.oracle_sort(U64, keys)
+    assert np.array_equal(out, want)
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+@pytest.mark.parametrize("dist", ["uniform", "few"])
+def test_oversized_groups_take_the_merge_fallback(api, pairs, dist):
+    # one level of 4 groups over 100000 keys with 1024-key leaves: every
+    # group is far larger than a leaf, so the base case merges sorted runs
+    n = 100000
+    keys = gen(U64, n, dist, 60)
+    p = api.make_params(levels=1, k=4, overpartition_b=1, leaf_capacity=1024)
+    log("fallback pairs=%s %s" % (pairs, dist))
+    if pairs:
+        vals = np.arange(n, dtype=np.uint32)
+        ok, ov = api.sort_pairs(to_dev(keys), to_dev(vals), params=p)
+        wk, wv = oracle.oracle_sort(U64, keys, vals)
+        assert np.array_equal(to_host(ok), wk) and np.array_equal(to_host(ov), wv)
+    else:
+        out = to_host(api.sort_keys(to_dev(keys), params=p))
+        want, _ = oracle.oracle_sort(U64, keys)
+        assert np.array_equal(out, want)
+
+
+def test_workspace_given_by_caller(api):
+    n = 200000
+    keys = gen(F32, n, "uniform", 70)
+    wsb = api.workspace_bytes(F32, n)
+    ws = api.alloc_workspace(wsb)
+    out = to_host(api.sort_keys(to_dev(keys), workspace=ws))
+    want, _ = oracle.oracle_sort(F32, keys)
+    assert np.array_equal(out.view(np.uint32), want.view(np.uint32))
+    from paper_1410_6754_amd import AmsError
+    with pytest.raises(AmsError):
+        api.sort_keys(to_dev(keys), workspace=api.alloc_workspace(wsb // 2))
+
+
+@pytest.mark.parametrize("kt", [U64, F32])
+def test_stable_partition_flag_same_result(api, kt):
+    # keys-only through the stable (ballot-ranked) scatter: same sorted output
+    n = 500000
+    keys = gen(kt, n, "few", 80)
+    p = api.make_params(flags=2, levels=2, k=64)
+    out = to_host(api.sort_keys(to_dev(keys), params=p))
+    want, _ = oracle.oracle_sort(kt, keys)
+    assert np.array_equal(out.view(np.uint8), want.view(np.uint8))
