@@ -1064,7 +1064,8 @@ template <typename K> struct FinSmem {
   K *B;             // C + FIN_PAD keys
   uint32_t *vB;     // C payloads (pairs only)
   uint8_t *bid;     // C: bucket index b of each staged key (equality bit recomputed)
-  uint32_t *bstart; // 2*FMAX + 4 bucket starts; bstart[2*FMAX+2] holds the largest bucket
+  uint32_t *bstart; // 2*FMAX + 4 bucket starts
+  uint32_t *wred;   // 2 * 8 words: per-wave totals and maxima of the bucket scan
   uint32_t *cnt;    // bucket counters (keys-only) or 8 per-wave rows (pairs)
   uint32_t *tmp;    // FIN_THREADS words of scan scratch (aliases cnt for keys-only)
   uint32_t *bm;     // C bits: placed positions (keys-only; aliases cnt)
@@ -1085,7 +1086,8 @@ template <typename K, bool PAY> AMS_DEV FinSmem<K> fin_smem(unsigned char *base,
   f.vB = (uint32_t *)(f.B + C + FIN_PAD);
   f.bid = (uint8_t *)(f.vB + (PAY ? C : 0));
   f.bstart = (uint32_t *)(f.bid + fin_bid_bytes<K>(C));
-  f.cnt = f.bstart + 2 * FMAX + 4;
+  f.wred = f.bstart + 2 * FMAX + 4;
+  f.cnt = f.wred + 16;
   f.tmp = PAY ? f.cnt + fin_cnt_words<K, PAY>() : f.cnt;
   f.bm = f.cnt;
   f.srt = (K *)(f.tmp + (PAY ? FIN_THREADS : fin_cnt_words<K, PAY>()));
@@ -1097,7 +1099,7 @@ template <typename K, bool PAY> AMS_DEV FinSmem<K> fin_smem(unsigned char *base,
 
 template <typename K, bool PAY> __host__ inline size_t fin_smem_bytes(uint32_t C) {
   return (size_t)(C + FIN_PAD) * sizeof(K) + (PAY ? (size_t)C * 4 : 0) + fin_bid_bytes<K>(C) +
-         (2 * FMAX + 4) * 4 + fin_cnt_words<K, PAY>() * 4 + (PAY ? FIN_THREADS * 4 : 0) +
+         (2 * FMAX + 4 + 16) * 4 + fin_cnt_words<K, PAY>() * 4 + (PAY ? FIN_THREADS * 4 : 0) +
          FMAX * sizeof(K);
 }
 
@@ -1165,6 +1167,8 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     while (f < need && f < FMAX) f <<= 1;
   }
   const uint32_t logf = ilog2c(f);
+  static_assert(2 * FMAX == FIN_THREADS, "one bucket counter per thread");
+  if (!PAY) sm.cnt[tid] = 0;  // keys-only bucket counters (the previous call ended on a barrier)
   const K *spl = sm.srt + 1;  // spl[b] = splitter just above bucket b
   K xk[FIN_KPT];
   uint32_t xv[FIN_KPT];
@@ -1181,38 +1185,69 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   }
   bool eq = false;
   if (f > 1) {
-    // stage the keys in input order and draw the sample from LDS
-#pragma unroll
-    for (uint32_t k = 0; k < FIN_KPT; ++k) {
-      const uint32_t p = PAY ? (wave * spw + k) * 64 + lane : tid + FIN_THREADS * k;
-      if (PAY ? (k < spw && p < s) : p < s) sm.B[p] = xk[k];
+    // f sampled keys, read straight from the source (the leaf's lines are
+    // being fetched by the loads above)
+    if (tid < f) {
+      const K y = src[draw_pos(st, tid, s)];
+      sm.smp[tid] = enc_in ? Key<KT>::enc(y) : y;
     }
     __syncthreads();
-    if (tid < f) sm.smp[tid] = sm.B[draw_pos(st, tid, s)];
-    __syncthreads();
+    // Rank the sample (Section 4.2): inside blocks of up to 64 by comparing
+    // all pairs, then across blocks by binary search.  H adjacent lanes share
+    // one sample and add their partial counts.  Ties are broken by index, so
+    // every sampled key gets a distinct rank.
     const uint32_t bsz = f < 64 ? f : 64, nbk = (f + 63) / 64;
-    if (tid < f) {
-      const uint32_t b0 = tid & ~63u;
-      const K x = sm.smp[tid];
-      uint32_t r = 0;
-      for (uint32_t q = 0; q < bsz; ++q) {
-        const K y = sm.smp[b0 + q];
-        r += (uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(b0 + q < tid));
+    const uint32_t H = FIN_THREADS / f < 8 ? FIN_THREADS / f : 8;
+    const uint32_t i = tid / H, part = tid % H;
+    const bool act = i < f;
+    {
+      const uint32_t b0 = act ? i & ~63u : 0u, iw = i & 63u;
+      const K x = sm.smp[act ? i : 0u];
+      const uint32_t chunk = (bsz + H - 1) / H;
+      const uint32_t j0 = part * chunk < bsz ? part * chunk : bsz;
+      const uint32_t j1 = j0 + chunk < bsz ? j0 + chunk : bsz;
+      uint32_t c[4] = {0, 0, 0, 0};
+      uint32_t j = j0;
+      for (; j + 4 <= j1; j += 4) {
+        K y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = sm.smp[b0 + j + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          c[u] += (uint32_t)(y[u] < x) | ((uint32_t)(y[u] == x) & (uint32_t)(j + u < iw));
       }
-      sm.blk[b0 + r] = x;
+      for (; j < j1; ++j) {
+        const K y = sm.smp[b0 + j];
+        c[0] += (uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(j < iw));
+      }
+      uint32_t r = (c[0] + c[1]) + (c[2] + c[3]);
+      for (uint32_t d = 1; d < H; d <<= 1) r += __shfl_xor(r, (int)d, 64);
+      if (act && part == 0) (nbk > 1 ? sm.blk : sm.srt)[b0 + r] = x;
     }
     __syncthreads();
-    if (tid < f) {
-      const uint32_t b = tid >> 6;
-      const K x = sm.blk[tid];
-      uint32_t r = tid & 63u;
-      for (uint32_t ob = 0; ob < nbk; ++ob) {
+    if (nbk > 1) {
+      // full blocks of 64 (f >= 128): lane part searches blocks part,
+      // part + H, ...; keys of an earlier block count when equal
+      const uint32_t b = act ? i >> 6 : 0u;
+      const K x = sm.blk[act ? i : 0u];
+      uint32_t r = part == 0 ? (i & 63u) : 0u;
+      for (uint32_t ob = part; ob < nbk; ob += H) {
         if (ob == b) continue;
-        r += ob < b ? count_less_eq(sm.blk + ob * 64, 64u, x) : count_less(sm.blk + ob * 64, 64u, x);
+        const K *a = sm.blk + ob * 64;
+        const bool le = ob < b;
+        uint32_t base = 0;
+#pragma unroll
+        for (uint32_t half = 32; half >= 1; half >>= 1) {
+          const K y = a[base + half - 1];
+          base = (y < x || (le && y == x)) ? base + half : base;
+        }
+        const K y = a[base];
+        r += base + ((y < x || (le && y == x)) ? 1u : 0u);
       }
-      sm.srt[r] = x;
+      for (uint32_t d = 1; d < H; d <<= 1) r += __shfl_xor(r, (int)d, 64);
+      if (act && part == 0) sm.srt[r] = x;
+      __syncthreads();
     }
-    __syncthreads();
     bool dup = false;
     if (tid >= 1 && tid < f) {
       sm.tree[eytzinger_slot(tid, f)] = sm.srt[tid];
@@ -1225,10 +1260,10 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     for (uint32_t k = 0; k < FIN_KPT; ++k) xir[k] = 0;
   }
   const uint32_t NB = f == 1 ? 1 : (eq ? 2 * f - 1 : f);
+  uint32_t Lb;  // largest bucket
   if (!PAY) {
     // ---- keys only: unstable split with LDS atomics ----
-    if (tid < NB) sm.cnt[tid] = 0;
-    __syncthreads();
+    if (f == 1) __syncthreads();  // counters were cleared on entry
 #pragma unroll
     for (uint32_t k = 0; k < FIN_KPT; ++k) {
       const uint32_t p = tid + FIN_THREADS * k;
@@ -1237,9 +1272,26 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       xir[k] = (xir[k] << 16) | slot;
     }
     __syncthreads();
-    if (tid < NB) sm.bstart[tid] = sm.cnt[tid];
+    // exclusive scan of the NB <= FIN_THREADS bucket sizes (one per thread)
+    // and the largest bucket, from per-wave totals and maxima
+    const uint32_t cv = tid < NB ? sm.cnt[tid] : 0u;
+    const uint32_t inc = wave_incl_scan(cv);
+    const uint32_t wmx = wave_max(cv);
+    if (lane == 63) {
+      sm.wred[wave] = inc;
+      sm.wred[8 + wave] = wmx;
+    }
     __syncthreads();
-    block_exscan<FIN_THREADS>(sm.bstart, NB, sm.tmp);
+    uint32_t off = 0;
+    Lb = 0;
+#pragma unroll
+    for (uint32_t ww = 0; ww < FIN_THREADS / 64; ++ww) {
+      off += ww < wave ? sm.wred[ww] : 0u;
+      Lb = sm.wred[8 + ww] > Lb ? sm.wred[8 + ww] : Lb;
+    }
+    if (tid < NB) sm.bstart[tid] = off + inc - cv;
+    if (tid == 0) sm.bstart[NB] = s;
+    __syncthreads();
 #pragma unroll
     for (uint32_t k = 0; k < FIN_KPT; ++k) {
       const uint32_t p = tid + FIN_THREADS * k;
@@ -1251,6 +1303,8 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       }
     }
     for (uint32_t w32 = tid; w32 < (C + 31) / 32; w32 += FIN_THREADS) sm.bm[w32] = 0;
+    if (s + Lb + 8 <= C + FIN_PAD)
+      for (uint32_t q = s + tid; q < s + Lb + 8; q += FIN_THREADS) sm.B[q] = (K)~(K)0;
   } else {
     // ---- pairs: stable split, ballot ranks inside each wave's range ----
     const uint32_t nbits = ilog2c(NB);
@@ -1299,108 +1353,90 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         sm.vB[q] = xv[k];
       }
     }
-  }
-  // largest bucket, for the sentinel pad
-  uint32_t *shMax = sm.bstart + 2 * FMAX + 2;
-  if (tid == 0) {
-    sm.bstart[NB] = s;
-    *shMax = 0;
-  }
-  __syncthreads();
-  if (tid < NB) atomicMax(shMax, sm.bstart[tid + 1] - sm.bstart[tid]);
-  __syncthreads();
-  const uint32_t Lb = *shMax;
-  const bool padded = s + Lb + 4 <= C + FIN_PAD;
-  if (padded)
-    for (uint32_t q = s + tid; q < s + Lb + 4; q += FIN_THREADS) sm.B[q] = (K)~(K)0;
-  __syncthreads();
-  // ---- all-pairs rank inside every bucket; two slots per pass, waves run a
-  // common trip count.  B is not modified while ranking, so every key goes
-  // straight to its final position in dst once its rank is known.
-#pragma unroll
-  for (uint32_t k = 0; k < FIN_KPT; k += 2) {
-    if (FIN_THREADS * k >= s) continue;  // uniform: slot pair holds no key
-    uint32_t q[2], bs[2], len[2], rk[2] = {0, 0}, v[2] = {0, 0};
-    K x[2];
-    bool isEq[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      q[h] = tid + FIN_THREADS * (k + h);
-      const bool valid = q[h] < s;
-      const uint32_t qs = valid ? q[h] : 0u;
-      x[h] = sm.B[qs];
-      const uint32_t b = sm.bid[qs];
-      const uint32_t id = eq ? 2 * b + ((b + 1 < f && x[h] == spl[b]) ? 1u : 0u) : b;
-      bs[h] = valid ? sm.bstart[id] : 0u;
-      const uint32_t be = valid ? sm.bstart[id + 1] : 0u;
-      isEq[h] = eq && (id & 1u);  // equal keys: any arrangement is final
-      len[h] = (valid && !isEq[h]) ? be - bs[h] : 0u;
-      if (PAY) v[h] = sm.vB[qs];
+    // largest bucket, for the sentinel pad
+    uint32_t *shMax = sm.wred;
+    if (tid == 0) {
+      sm.bstart[NB] = s;
+      *shMax = 0;
     }
-    const uint32_t ml = wave_max(len[0] > len[1] ? len[0] : len[1]);
+    __syncthreads();
+    if (tid < NB) atomicMax(shMax, sm.bstart[tid + 1] - sm.bstart[tid]);
+    __syncthreads();
+    Lb = *shMax;
+    if (s + Lb + 8 <= C + FIN_PAD)
+      for (uint32_t q = s + tid; q < s + Lb + 8; q += FIN_THREADS) sm.B[q] = (K)~(K)0;
+  }
+  __syncthreads();
+  // scans of at most Lb + 7 slots past a bucket start stay inside B
+  const bool padded = s + Lb + 8 <= C + FIN_PAD;
+  // ---- all-pairs rank inside every bucket, one slot of FIN_THREADS keys
+  // per pass; a wave's lanes run a common trip count (the longest bucket
+  // among them).  B is not modified while ranking, so every key goes
+  // straight to its final position in dst once its rank is known.
+#pragma unroll 1
+  for (uint32_t k = 0; k < FIN_KPT; ++k) {
+    if (FIN_THREADS * k >= s) break;  // uniform: no key in this or later slots
+    const uint32_t q = tid + FIN_THREADS * k;
+    const bool valid = q < s;
+    const uint32_t qs = valid ? q : 0u;
+    const K x = sm.B[qs];
+    const uint32_t b = sm.bid[qs];
+    const uint32_t id = eq ? 2 * b + ((b + 1 < f && x == spl[b]) ? 1u : 0u) : b;
+    const uint32_t bs = valid ? sm.bstart[id] : 0u;
+    const uint32_t be = valid ? sm.bstart[id + 1] : 0u;
+    const bool isEq = eq && (id & 1u);  // equal keys: any arrangement is final
+    const uint32_t len = (valid && !isEq) ? be - bs : 0u;
+    const uint32_t v = PAY ? sm.vB[qs] : 0u;
+    // wave-uniform trip count, held in a scalar register
+    const uint32_t ml = __builtin_amdgcn_readfirstlane(wave_max(len));
+    uint32_t rk = 0;
     if (padded) {
-      const K *a0 = sm.B + bs[0];
-      const K *a1 = sm.B + bs[1];
+      const K *a = sm.B + bs;
+      // one counter per unrolled element: each compare then feeds a single
+      // add-with-carry instead of a packed mask and a population count
+      uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (!PAY) {
-        for (uint32_t d = 0; d < ml; d += 4) {
-          K y0[4], y1[4];
+        for (uint32_t d = 0; d < ml; d += 8) {
+          K y[8];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            y0[u] = a0[d + u];
-            y1[u] = a1[d + u];
-          }
+          for (int u = 0; u < 8; ++u) y[u] = a[d + u];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            rk[0] += (uint32_t)(y0[u] < x[0]);
-            rk[1] += (uint32_t)(y1[u] < x[1]);
-          }
+          for (int u = 0; u < 8; ++u) c[u] += (uint32_t)(y[u] < x);
         }
       } else {
-        const uint32_t qb0 = q[0] - bs[0], qb1 = q[1] - bs[1];  // j < q  <=>  d + u < qb
-        for (uint32_t d = 0; d < ml; d += 4) {
-          K y0[4], y1[4];
+        const uint32_t qb = q - bs;  // j < q  <=>  d + u < qb
+        for (uint32_t d = 0; d < ml; d += 8) {
+          K y[8];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            y0[u] = a0[d + u];
-            y1[u] = a1[d + u];
-          }
+          for (int u = 0; u < 8; ++u) y[u] = a[d + u];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            rk[0] += (uint32_t)(y0[u] < x[0]) | ((uint32_t)(y0[u] == x[0]) & (uint32_t)(d + u < qb0));
-            rk[1] += (uint32_t)(y1[u] < x[1]) | ((uint32_t)(y1[u] == x[1]) & (uint32_t)(d + u < qb1));
-          }
+          for (int u = 0; u < 8; ++u)
+            c[u] += (uint32_t)(y[u] < x) | ((uint32_t)(y[u] == x) & (uint32_t)(d + u < qb));
         }
       }
+      rk = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
     } else {
+      for (uint32_t d = 0; d < ml; d += 4) {
+        K y[4];
+        uint32_t jj[4];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint32_t mh = wave_max(len[h]);
-        const uint32_t qs = q[h] < s ? q[h] : 0u;
-        for (uint32_t d = 0; d < mh; d += 4) {
-          K y[4];
-          uint32_t jj[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            jj[u] = d + u < len[h] ? bs[h] + d + u : qs;
-            y[u] = sm.B[jj[u]];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            rk[h] += (uint32_t)(d + u < len[h]) &
-                     ((uint32_t)(y[u] < x[h]) | ((uint32_t)(y[u] == x[h]) & (uint32_t)(jj[u] < q[h])));
+        for (int u = 0; u < 4; ++u) {
+          jj[u] = d + u < len ? bs + d + u : qs;
+          y[u] = sm.B[jj[u]];
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          rk += (uint32_t)(d + u < len) &
+                ((uint32_t)(y[u] < x) | ((uint32_t)(y[u] == x) & (uint32_t)(jj[u] < q)));
       }
     }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (q[h] >= s) continue;
-      uint32_t pos = isEq[h] ? q[h] : bs[h] + rk[h];
-      const K out = dec_out ? Key<KT>::dec(x[h]) : x[h];
-      if (!PAY && !isEq[h] && !padded) {
-        // masked path ranks with the position tie-break: ranks are unique
-      } else if (!PAY && !isEq[h]) {
+    if (valid) {
+      uint32_t pos = isEq ? q : bs + rk;
+      const K out = dec_out ? Key<KT>::dec(x) : x;
+      if (!PAY && !isEq && padded) {
         // keys sharing a rank are equal bits: the first claims the rank,
-        // the others claim the empty positions right after it
+        // the others claim the empty positions right after it (the masked
+        // path ranks with the position tie-break, so its ranks are unique)
         uint32_t old = atomicOr(&sm.bm[pos >> 5], 1u << (pos & 31u));
         while (old & (1u << (pos & 31u))) {
           ++pos;
@@ -1408,7 +1444,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         }
       }
       dst[pos] = out;
-      if (PAY) vdst[pos] = v[h];
+      if (PAY) vdst[pos] = v;
     }
   }
   __syncthreads();
@@ -1670,7 +1706,8 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     return AMS_EINVAL;
   }
   const uint32_t Scap = 65536 / pl.kw;
-  // levels: enough that an average group fits half of the leaf capacity
+  // levels: enough that an average group fills at most 55% of the leaf
+  // capacity; the rest absorbs the imbalance of the grouping at each level
   uint32_t L = 0;
   if (mx > C) {
     if (p && p->levels) {
@@ -1678,7 +1715,7 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     } else {
       L = 1;
       double cap = (double)r;
-      while (L < MAXLEV && (double)mx / cap > C / 2.0) {
+      while (L < MAXLEV && (double)mx / cap > 0.55 * C) {
         ++L;
         cap *= r;
       }
