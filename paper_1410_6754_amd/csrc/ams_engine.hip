@@ -495,16 +495,13 @@ AMS_DEV Greedy greedy_scan(const uint32_t *wgt, uint32_t nb, uint32_t L, uint32_
     const uint4 a = w4[2 * j], b = w4[2 * j + 1];
     const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 8; ++u) {  // branch-free: selects only
       const uint32_t t = cur + v[u];
-      if (t > L) {
-        zmin = min(zmin, t);
-        maxG = max(maxG, cur);
-        ++groups;
-        cur = v[u];
-      } else {
-        cur = t;
-      }
+      const bool o = t > L;
+      zmin = o ? min(zmin, t) : zmin;
+      maxG = o ? max(maxG, cur) : maxG;
+      groups += o ? 1u : 0u;
+      cur = o ? v[u] : t;
     }
   }
   maxG = max(maxG, cur);
@@ -574,71 +571,127 @@ struct PackSmem {
   uint32_t *tot, *wgt, *sz, *start, *tmp, *red;
   uint16_t *first, *end;
   uint8_t *fin, *kind;
+  uint32_t *aux;  // HS + 1 words of scan space
+  uint16_t *pst;  // HS + 1 piece starts
+  uint8_t *gs;    // HS + 8 flags: the greedy opens a group at this id
 };
 
+AMS_HD size_t pack_al16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// LDS layout of k_pack (byte offsets rounded to 16); returns the total size
+AMS_HD size_t pack_layout(uint32_t HS, uint32_t CH, size_t *o) {
+  size_t b = 0;
+  o[0] = b; b = pack_al16(b + (size_t)HS * 4);            // tot
+  o[1] = b; b = pack_al16(b + ((size_t)HS + 8) * 4);      // wgt, zero-padded to 8
+  o[2] = b; b = pack_al16(b + ((size_t)CH + 1) * 4);      // sz
+  o[3] = b; b = pack_al16(b + ((size_t)CH + 1) * 4);      // start
+  o[4] = b; b = pack_al16(b + 256 * 4);                   // tmp
+  o[5] = b; b = pack_al16(b + 16 * 4);                    // red
+  o[6] = b; b = pack_al16(b + ((size_t)CH + 1) * 2);      // first
+  o[7] = b; b = pack_al16(b + ((size_t)CH + 1) * 2);      // end
+  o[8] = b; b = pack_al16(b + ((size_t)HS + 1) * 4);      // aux
+  o[9] = b; b = pack_al16(b + ((size_t)HS + 1) * 2);      // pst
+  o[10] = b; b = pack_al16(b + HS);                       // fin
+  o[11] = b; b = pack_al16(b + CH);                       // kind
+  o[12] = b; b = pack_al16(b + (size_t)HS + 8);           // gs
+  return b;
+}
+
 AMS_DEV PackSmem pack_smem(unsigned char *base, uint32_t HS, uint32_t CH) {
+  size_t o[13];
+  pack_layout(HS, CH, o);
   PackSmem p;
-  p.tot = (uint32_t *)base;
-  p.wgt = p.tot + HS;
-  p.sz = p.wgt + HS + 8;  // weights are zero-padded to a multiple of 8
-  p.start = p.sz + CH + 1;
-  p.tmp = p.start + CH + 1;
-  p.red = p.tmp + 256;
-  p.first = (uint16_t *)(p.red + 16);
-  p.end = p.first + CH + 1;
-  p.fin = (uint8_t *)(p.end + CH + 1);
-  p.kind = p.fin + HS;
+  p.tot = (uint32_t *)(base + o[0]);
+  p.wgt = (uint32_t *)(base + o[1]);
+  p.sz = (uint32_t *)(base + o[2]);
+  p.start = (uint32_t *)(base + o[3]);
+  p.tmp = (uint32_t *)(base + o[4]);
+  p.red = (uint32_t *)(base + o[5]);
+  p.first = (uint16_t *)(base + o[6]);
+  p.end = (uint16_t *)(base + o[7]);
+  p.aux = (uint32_t *)(base + o[8]);
+  p.pst = (uint16_t *)(base + o[9]);
+  p.fin = base + o[10];
+  p.kind = base + o[11];
+  p.gs = base + o[12];
   return p;
 }
 
-// Children of one subproblem from its id totals (in p.tot), by thread 0:
-// greedy groups under L, cut at final equality buckets; returns the count.
+// Children of one subproblem from its id totals (p.tot), weights (p.wgt)
+// and final flags (p.fin), by the whole block of NT threads:
+//  1. one lane runs the greedy under L and flags the ids that open a group
+//     (final ids weigh 0 and never open one);
+//  2. pieces start at id 0, at group starts, at every final id and right
+//     after it; a final id is a child of its own (CHILD_FINAL), any other
+//     piece is a CHILD_REG child if it holds keys and is dropped otherwise
+//     (its ids then fall to the child before it).
+// Returns the number of children; p.aux[NB] holds the total key count.
+template <int NT>
 AMS_DEV uint32_t build_children(const PackSmem &p, uint32_t NB, uint32_t L, uint32_t CH) {
-  uint32_t cur = 0, pf = 0, psz = 0, nch = 0;
-  uint32_t wv[8], tv[8];
-  uint8_t fv[8];
-  for (uint32_t j = 0; j < NB && nch + 2 < CH; ++j) {
-    if ((j & 7u) == 0) {  // fetch the next eight ids ahead of the scan
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) {
+    uint32_t cur = 0;
+    const uint4 *w4 = (const uint4 *)p.wgt;
+    for (uint32_t j0 = 0; j0 < NB; j0 += 8) {
+      const uint4 a = w4[j0 / 4], b = w4[j0 / 4 + 1];
+      const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      uint32_t bits = 0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const uint32_t jj = j + u < NB ? j + u : NB - 1;
-        wv[u] = p.wgt[jj];
-        tv[u] = p.tot[jj];
-        fv[u] = p.fin[jj];
+        const uint32_t t = cur + v[u];
+        const bool o = t > L;
+        cur = o ? v[u] : t;
+        bits |= (o ? 1u : 0u) << (8 * (u & 3));
+        if (u == 3 || u == 7) {
+          *(uint32_t *)(p.gs + j0 + (u & 4)) = bits;  // gs is 4-byte aligned
+          bits = 0;
+        }
       }
-    }
-    const uint32_t wj = wv[j & 7u];
-    if (cur + wj > L) {
-      if (psz) {
-        p.first[nch] = pf; p.end[nch] = j; p.sz[nch] = psz; p.kind[nch] = CHILD_REG; ++nch;
-      }
-      pf = j;
-      psz = 0;
-      cur = 0;
-    }
-    cur += wj;
-    if (fv[j & 7u]) {
-      if (psz) {
-        p.first[nch] = pf; p.end[nch] = j; p.sz[nch] = psz; p.kind[nch] = CHILD_REG; ++nch;
-      }
-      p.first[nch] = j; p.end[nch] = j + 1; p.sz[nch] = tv[j & 7u]; p.kind[nch] = CHILD_FINAL; ++nch;
-      pf = j + 1;
-      psz = 0;
-    } else {
-      psz += tv[j & 7u];
     }
   }
-  if (psz && nch < CH) {
-    p.first[nch] = pf; p.end[nch] = NB; p.sz[nch] = psz; p.kind[nch] = CHILD_REG; ++nch;
+  __syncthreads();
+  // piece starts, numbered by a scan
+  for (uint32_t j = tid; j < NB; j += NT)
+    p.aux[j] = (j == 0 || p.gs[j] || p.fin[j] || p.fin[j - 1]) ? 1u : 0u;
+  __syncthreads();
+  const uint32_t np = block_exscan<NT>(p.aux, NB, p.tmp);
+  for (uint32_t j = tid; j < NB; j += NT)
+    if (j == 0 || p.gs[j] || p.fin[j] || p.fin[j - 1]) p.pst[p.aux[j]] = (uint16_t)j;
+  if (tid == 0) p.pst[np] = (uint16_t)NB;
+  // key counts before every id
+  for (uint32_t j = tid; j < NB; j += NT) p.aux[j] = p.tot[j];
+  __syncthreads();
+  const uint32_t total = block_exscan<NT>(p.aux, NB, p.tmp);
+  if (tid == 0) p.aux[NB] = total;
+  __syncthreads();
+  // kept pieces, numbered by a scan over the pieces (p.start as space)
+  for (uint32_t q = tid; q < np; q += NT) {
+    const uint32_t a = p.pst[q], b = p.pst[q + 1];
+    p.start[q] = (p.fin[a] || p.aux[b] > p.aux[a]) ? 1u : 0u;
   }
-  return nch;
+  __syncthreads();
+  // pieces number at most 3r = CH: r groups, r final ids (each holds at
+  // least N/r keys), and the pieces right after final ids
+  const uint32_t nch = block_exscan<NT>(p.start, np < CH ? np : CH, p.tmp);
+  for (uint32_t q = tid; q < np && q < CH; q += NT) {
+    const uint32_t a = p.pst[q], b = p.pst[q + 1];
+    const bool fin = p.fin[a] != 0;
+    if (fin || p.aux[b] > p.aux[a]) {
+      const uint32_t c = p.start[q];
+      p.first[c] = (uint16_t)a;
+      p.end[c] = (uint16_t)b;
+      p.sz[c] = p.aux[b] - p.aux[a];
+      p.kind[c] = fin ? CHILD_FINAL : CHILD_REG;
+    }
+  }
+  __syncthreads();
+  return np <= CH ? nch : CH + 1;  // CH + 1: cannot happen, reported as an overflow
 }
 
 __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const uint32_t HS = lv.HS, CH = lv.CH;
   PackSmem p = pack_smem(smem_raw, HS, CH);
-  __shared__ uint32_t sN;
   const uint32_t tid = threadIdx.x;
   const uint32_t P = w.ctr->P;
   for (uint32_t i = blockIdx.x; i < P; i += gridDim.x) {
@@ -659,15 +712,11 @@ __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
     }
     __syncthreads();
     const uint32_t L = optimal_load<256>(p.wgt, NB, r, p.red);
-    if (tid == 0) {
-      uint32_t nch = build_children(p, NB, L, CH);
-      uint32_t got = 0;
-      for (uint32_t c = 0; c < nch; ++c) got += p.sz[c];
-      if (got != N) atomicOr(&w.ctr->overflow, 8u);  // cannot happen: nch <= 3r = CH
-      sN = nch;
+    uint32_t nch = build_children<256>(p, NB, L, CH);
+    if (nch > CH || p.aux[NB] != N) {  // cannot happen: at most 3r = CH children
+      if (tid == 0) atomicOr(&w.ctr->overflow, 8u);
+      nch = 0;
     }
-    __syncthreads();
-    const uint32_t nch = sN;
     if (w.dbgHist && lv.level == 0 && i == 0) {
       for (uint32_t id = tid; id < NB; id += 256) w.dbgHist[id] = p.tot[id];
       for (uint32_t c = tid; c < nch; c += 256) {
@@ -941,27 +990,54 @@ AMS_DEV void sck_load(const typename Key<KT>::T *src, uint32_t cb, uint32_t hi,
   }
 }
 
+// Out-of-place exclusive scan of in[0..n) into out by a block of NT threads
+// (tmp: NT/64 words of LDS); same scheme as block_exscan.
+template <int NT>
+AMS_DEV void block_exscan_to(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tmp) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  constexpr uint32_t NW = NT / 64;
+  const uint32_t per = (n + NT - 1) / NT;
+  const uint32_t lo = tid * per < n ? tid * per : n;
+  const uint32_t hi = lo + per < n ? lo + per : n;
+  uint32_t s = 0;
+  for (uint32_t i = lo; i < hi; ++i) s += in[i];
+  const uint32_t incl = wave_incl_scan(s);
+  if (lane == 63) tmp[wave] = incl;
+  __syncthreads();
+  uint32_t off = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < NW; ++w) off += w < wave ? tmp[w] : 0u;
+  uint32_t run = off + incl - s;
+  for (uint32_t i = lo; i < hi; ++i) {
+    out[i] = run;
+    run += in[i];
+  }
+  __syncthreads();
+}
+
 template <int KT, int KPT>
-__global__ void __launch_bounds__(SCK_THREADS) k_scatter_keys(Ws w, Lev lv) {
+__global__ void __launch_bounds__(SCK_THREADS, 4) k_scatter_keys(Ws w, Lev lv) {
   typedef typename Key<KT>::T K;
   constexpr uint32_t CHK = SCK_THREADS * KPT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const uint32_t CH = lv.CH;
   K *sTree = (K *)smem_raw;                       // mmax
   K *stK = sTree + lv.mmax;                       // CHK
-  uint16_t *stC = (uint16_t *)(stK + CHK);        // CHK
+  uint64_t *sDst = (uint64_t *)(stK + CHK);       // CH: output address of chunk slot 0, per child
+  uint16_t *stC = (uint16_t *)(sDst + CH);        // CHK
   uint16_t *sI2C = stC + CHK;                     // HS
   uint32_t *sBase = (uint32_t *)(sI2C + lv.HS);   // CH
-  uint32_t *sL = sBase + CH;                      // CH + 1
-  uint32_t *sCnt = sL + CH + 1;                   // CH
-  uint32_t *sTmp = sCnt + CH;                     // SCK_THREADS
-  uint8_t *sCd = (uint8_t *)(sTmp + SCK_THREADS); // CH
+  uint32_t *sL = sBase + CH;                      // CH
+  uint32_t *sCnt = sL + CH;                       // CH
+  uint32_t *sTmp = sCnt + CH;                     // SCK_THREADS / 64
+  uint8_t *sCd = (uint8_t *)(sTmp + SCK_THREADS / 64);  // CH
   const uint32_t tid = threadIdx.x;
   const uint32_t P = w.ctr->P;
   ItemRange ir = xcd_items(w.ctr->ntile);
   uint32_t cur = 0xFFFFFFFFu, logm = 0, nch = 0;
   bool eq = false;
   const K *gSpl = nullptr;
+  for (uint32_t c = tid; c < CH; c += SCK_THREADS) sCnt[c] = 0;
   for (uint32_t g = ir.first; g < ir.end; g += ir.step) {
     const uint32_t i = find_owner(w.tileStart, P, g);
     const uint32_t t = g - w.tileStart[i];
@@ -990,12 +1066,13 @@ __global__ void __launch_bounds__(SCK_THREADS) k_scatter_keys(Ws w, Lev lv) {
       gSpl = (const K *)w.spl + (size_t)i * lv.mmax;
       cur = i;
     }
+    // sBase[c]: this tile's next output offset of child c (read and
+    // advanced only by thread c % SCK_THREADS)
     for (uint32_t c = tid; c < nch; c += SCK_THREADS) sBase[c] = w.tileOff[(size_t)g * CH + c];
+    __syncthreads();
     for (uint32_t cb = lo; cb < hi; cb += CHK) {
       K xb[KPT];
       if (cb + CHK < hi) sck_load<KT, KPT>(src, cb + CHK, hi, xb);
-      for (uint32_t c = tid; c < nch; c += SCK_THREADS) sCnt[c] = 0;
-      __syncthreads();
       if (enc) {
 #pragma unroll
         for (int k = 0; k < KPT; ++k) xa[k] = Key<KT>::enc(xa[k]);
@@ -1013,9 +1090,22 @@ __global__ void __launch_bounds__(SCK_THREADS) k_scatter_keys(Ws w, Lev lv) {
         xcs[k] = (c << 16) | slot;
       }
       __syncthreads();
-      for (uint32_t c = tid; c < nch; c += SCK_THREADS) sL[c] = sCnt[c];
-      __syncthreads();
-      block_exscan<SCK_THREADS>(sL, nch, sTmp);
+      block_exscan_to<SCK_THREADS>(sCnt, sL, nch, sTmp);
+      // per child: the output address of chunk slot 0 (low bit: decode the
+      // key on the way out; 0: the child would overrun its subproblem and
+      // its keys are dropped, flagged as an overflow); then advance sBase
+      for (uint32_t c = tid; c < nch; c += SCK_THREADS) {
+        const uint32_t cd = sCd[c];
+        uint64_t d = 0;
+        if ((uint64_t)sBase[c] + sCnt[c] <= s.size) {
+          const K *base = kptr<K>(w, R, cd & 15u) + s.off + sBase[c];
+          d = ((uint64_t)(uintptr_t)base - (uint64_t)sL[c] * sizeof(K)) | (uint64_t)(cd >> 4);
+        } else {
+          atomicOr(&w.ctr->overflow, 16u);
+        }
+        sDst[c] = d;
+        sBase[c] += sCnt[c];
+      }
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
         const uint32_t p = cb + tid + SCK_THREADS * k;
@@ -1027,21 +1117,27 @@ __global__ void __launch_bounds__(SCK_THREADS) k_scatter_keys(Ws w, Lev lv) {
         }
       }
       __syncthreads();
+      // write out: consecutive slots of a child go to consecutive addresses
       const uint32_t cnt = hi - cb < CHK ? hi - cb : CHK;
-      for (uint32_t q = tid; q < cnt; q += SCK_THREADS) {
-        const uint32_t c = stC[q];
-        const uint32_t rel = sBase[c] + (q - sL[c]);
-        if (rel >= s.size) {  // defensive: never write outside the subproblem
-          atomicOr(&w.ctr->overflow, 16u);
-          continue;
-        }
-        const uint32_t cd = sCd[c];
-        K x = stK[q];
-        if (cd >> 4) x = Key<KT>::dec(x);
-        kptr<K>(w, R, cd & 15u)[s.off + rel] = x;
+      uint32_t cc[KPT];
+      K xo[KPT];
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const uint32_t q = tid + SCK_THREADS * k;
+        cc[k] = q < cnt ? stC[q] : 0u;
+        xo[k] = q < cnt ? stK[q] : (K)0;
       }
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const uint32_t q = tid + SCK_THREADS * k;
+        const uint64_t d = q < cnt ? sDst[cc[k]] : 0ull;
+        if (d) {
+          const K x = (d & 1u) ? Key<KT>::dec(xo[k]) : xo[k];
+          *(K *)((d & ~(uint64_t)1) + (uint64_t)q * sizeof(K)) = x;
+        }
+      }
+      for (uint32_t c = tid; c < nch; c += SCK_THREADS) sCnt[c] = 0;
       __syncthreads();
-      for (uint32_t c = tid; c < nch; c += SCK_THREADS) sBase[c] += sCnt[c];
 #pragma unroll
       for (int k = 0; k < KPT; ++k) xa[k] = xb[k];
     }
@@ -1070,7 +1166,7 @@ template <typename K> struct FinSmem {
   uint32_t *tmp;    // FIN_THREADS words of scan scratch (aliases cnt for keys-only)
   uint32_t *bm;     // C bits: placed positions (keys-only; aliases cnt)
   K *srt;           // FMAX sorted samples; srt[1..f-1] are the splitters
-  K *smp, *blk, *tree;  // overlays in the bid region: samples, block-sorted samples, tree
+  K *smp, *blk, *tree;  // overlays in the bid region: sample, block-sorted sample, tree
 };
 
 template <typename K, bool PAY> AMS_HD size_t fin_cnt_words() { return PAY ? 8 * 2 * FMAX : 2 * FMAX; }
@@ -1091,7 +1187,9 @@ template <typename K, bool PAY> AMS_DEV FinSmem<K> fin_smem(unsigned char *base,
   f.tmp = PAY ? f.cnt + fin_cnt_words<K, PAY>() : f.cnt;
   f.bm = f.cnt;
   f.srt = (K *)(f.tmp + (PAY ? FIN_THREADS : fin_cnt_words<K, PAY>()));
-  f.smp = (K *)f.bid;  // sample overlays live in the bucket-id region until staging
+  // sample overlays live in the bucket-id region until the split: the
+  // sample, its sorted blocks and the splitter tree (FMAX keys each)
+  f.smp = (K *)f.bid;
   f.blk = f.smp + FMAX;
   f.tree = f.smp + 2 * FMAX;
   return f;
@@ -1139,10 +1237,47 @@ AMS_DEV void classify_halves(K (&x)[FIN_KPT], uint32_t (&id)[FIN_KPT], const K *
   }
 }
 
+// Part of the rank of x (from block b of nbk sorted blocks of 64 keys) among
+// the keys of the other blocks: this lane searches blocks part, part + H, ...
+// (T of them), side by side one halving step per round so that the LDS reads
+// of a round overlap.  Keys of an earlier block count when equal.  A block
+// that is b or past nbk is searched at block 0 (valid addresses) and its
+// count dropped.
+template <typename K, uint32_t T>
+AMS_DEV uint32_t cross_block_rank(const K *blk, uint32_t b, K x, uint32_t part, uint32_t H,
+                                  uint32_t nbk) {
+  uint32_t base[T], ob[T];
+  bool use[T];
+#pragma unroll
+  for (uint32_t t = 0; t < T; ++t) {
+    const uint32_t o = part + t * H;
+    use[t] = o < nbk && o != b;
+    ob[t] = o < nbk ? o : 0u;
+    base[t] = 0;
+  }
+#pragma unroll
+  for (uint32_t half = 32; half >= 1; half >>= 1) {
+#pragma unroll
+    for (uint32_t t = 0; t < T; ++t) {
+      const K y = blk[ob[t] * 64 + base[t] + half - 1];
+      base[t] += (y < x || (ob[t] < b && y == x)) ? half : 0u;
+    }
+  }
+  uint32_t r = 0;
+#pragma unroll
+  for (uint32_t t = 0; t < T; ++t) {
+    const K y = blk[ob[t] * 64 + base[t]];
+    const uint32_t c = base[t] + ((y < x || (ob[t] < b && y == x)) ? 1u : 0u);
+    r += use[t] ? c : 0u;
+  }
+  return r;
+}
+
 // Sort s <= C keys from src into dst inside one workgroup.
-//  1. f sampled keys are ranked: blocks of 64 by comparing all pairs, then
-//     across blocks by binary search (Section 4.2); srt[1..f-1] become the
-//     splitters of an f-way split (equality buckets if splitters repeat).
+//  1. a*f sampled keys are ranked: blocks of 64 by comparing all pairs, then
+//     across blocks by binary search (Section 4.2); the elements of rank
+//     a*j - 1 (j = 1..f-1) become srt[j], the splitters of an f-way split
+//     (equality buckets if splitters repeat).
 //  2. Every key is classified and placed in LDS by bucket (keys-only: LDS
 //     atomics, order inside a bucket arbitrary since equal keys are equal
 //     bits; pairs: ballot ranks, input order kept).
@@ -1185,9 +1320,16 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   }
   bool eq = false;
   if (f > 1) {
-    // f sampled keys, read straight from the source (the leaf's lines are
-    // being fetched by the loads above)
-    if (tid < f) {
+    // S = a*f sampled keys, read straight from the source (the leaf's lines
+    // are being fetched by the loads above); the splitters are the sorted
+    // sample's elements of rank a*j - 1, j = 1..f-1.  At most FMAX samples:
+    // ranking a larger sample costs more than the better balanced buckets
+    // save in the all-pairs step.  Sizes are powers of two (shifts only).
+    const uint32_t loga = logf <= 6 ? 2u : 8u - logf;   // a = 4, 2, 1
+    const uint32_t logS = logf + loga;                   // S <= FMAX = 256
+    const uint32_t logH = 9u - logS < 3u ? 9u - logS : 3u;  // H = min(512 / S, 8)
+    const uint32_t S = 1u << logS, H = 1u << logH, amask = (1u << loga) - 1u;
+    if (tid < S) {
       const K y = src[draw_pos(st, tid, s)];
       sm.smp[tid] = enc_in ? Key<KT>::enc(y) : y;
     }
@@ -1196,14 +1338,13 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     // all pairs, then across blocks by binary search.  H adjacent lanes share
     // one sample and add their partial counts.  Ties are broken by index, so
     // every sampled key gets a distinct rank.
-    const uint32_t bsz = f < 64 ? f : 64, nbk = (f + 63) / 64;
-    const uint32_t H = FIN_THREADS / f < 8 ? FIN_THREADS / f : 8;
-    const uint32_t i = tid / H, part = tid % H;
-    const bool act = i < f;
+    const uint32_t bsz = S < 64 ? S : 64, nbk = (S + 63) >> 6;
+    const uint32_t i = tid >> logH, part = tid & (H - 1u);
+    const bool act = i < S;
     {
       const uint32_t b0 = act ? i & ~63u : 0u, iw = i & 63u;
       const K x = sm.smp[act ? i : 0u];
-      const uint32_t chunk = (bsz + H - 1) / H;
+      const uint32_t chunk = (bsz + H - 1) >> logH;
       const uint32_t j0 = part * chunk < bsz ? part * chunk : bsz;
       const uint32_t j1 = j0 + chunk < bsz ? j0 + chunk : bsz;
       uint32_t c[4] = {0, 0, 0, 0};
@@ -1222,30 +1363,25 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       }
       uint32_t r = (c[0] + c[1]) + (c[2] + c[3]);
       for (uint32_t d = 1; d < H; d <<= 1) r += __shfl_xor(r, (int)d, 64);
-      if (act && part == 0) (nbk > 1 ? sm.blk : sm.srt)[b0 + r] = x;
+      if (act && part == 0) {
+        if (nbk > 1) sm.blk[b0 + r] = x;
+        else if (((r + 1) & amask) == 0 && ((r + 1) >> loga) < f) sm.srt[(r + 1) >> loga] = x;
+      }
     }
     __syncthreads();
     if (nbk > 1) {
-      // full blocks of 64 (f >= 128): lane part searches blocks part,
-      // part + H, ...; keys of an earlier block count when equal
+      // full blocks of 64 (S = 128 or 256): the H lanes of a sample split
+      // the other blocks among them (see cross_block_rank); a wave ranks
+      // keys of one block
       const uint32_t b = act ? i >> 6 : 0u;
       const K x = sm.blk[act ? i : 0u];
-      uint32_t r = part == 0 ? (i & 63u) : 0u;
-      for (uint32_t ob = part; ob < nbk; ob += H) {
-        if (ob == b) continue;
-        const K *a = sm.blk + ob * 64;
-        const bool le = ob < b;
-        uint32_t base = 0;
-#pragma unroll
-        for (uint32_t half = 32; half >= 1; half >>= 1) {
-          const K y = a[base + half - 1];
-          base = (y < x || (le && y == x)) ? base + half : base;
-        }
-        const K y = a[base];
-        r += base + ((y < x || (le && y == x)) ? 1u : 0u);
-      }
+      static_assert(FMAX == 256, "a sample of at most 4 blocks");
+      uint32_t r = nbk * 2 > H ? cross_block_rank<K, 2>(sm.blk, b, x, part, H, nbk)
+                               : cross_block_rank<K, 1>(sm.blk, b, x, part, H, nbk);
       for (uint32_t d = 1; d < H; d <<= 1) r += __shfl_xor(r, (int)d, 64);
-      if (act && part == 0) sm.srt[r] = x;
+      r += i & 63u;
+      if (act && part == 0 && ((r + 1) & amask) == 0 && ((r + 1) >> loga) < f)
+        sm.srt[(r + 1) >> loga] = x;
       __syncthreads();
     }
     bool dup = false;
@@ -1936,8 +2072,8 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
       hipLaunchKernelGGL(k_block_scan, dim3(grid_for((uint64_t)ls.P * ((ls.HS + 255) / 256), 1024)),
                          dim3(256), 0, s, w, lv);
     }
-    size_t ldsP = (size_t)ls.HS * 4 * 2 + 32 + (size_t)(ls.CH + 1) * 4 * 2 + 256 * 4 + 16 * 4 +
-                  (size_t)(ls.CH + 1) * 2 * 2 + ls.HS + ls.CH + 64;
+    size_t po[13];
+    size_t ldsP = pack_layout(ls.HS, ls.CH, po);
     allow_lds(k_pack, ldsP);
     {
       TraceScope ts("pack", l, s);
@@ -1969,8 +2105,8 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
     } else {
       constexpr int KPT = 8;
       constexpr uint32_t CHK = SCK_THREADS * KPT;
-      size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + CHK * 2 + (size_t)ls.HS * 2 +
-                    (size_t)ls.CH * 4 * 3 + 4 + SCK_THREADS * 4 + ls.CH + 64;
+      size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + (size_t)ls.CH * 8 + CHK * 2 +
+                    (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + SCK_THREADS / 64 * 4 + ls.CH + 64;
       allow_lds(k_scatter_keys<KT, KPT>, ldsS);
       TraceScope ts("scatter", l, s);
       hipLaunchKernelGGL((k_scatter_keys<KT, KPT>), dim3(grid_for(ls.tiles, 512)),
