@@ -93,8 +93,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
-    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--cpu-sample-log2", type=int, default=27)
     ap.add_argument("--trace-file", default=None, help="write the per-kernel table here")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device-to-device copy three times (the known-size "
+                         "kernel that scales the HBM byte counters), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -103,6 +106,16 @@ def main() -> int:
         return 2
 
     import torch
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.int64, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                          "launches": 3}))
+        return 0
 
     from paper_1410_6754_amd import api
 
