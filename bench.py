@@ -44,6 +44,12 @@ WORKLOADS = {
     "pairs_equal_2^27": (1 << 27, W.KEY_U64, "equal", True, dict(), 3),
 }
 DEFAULT = "uniform_u64_2^28"
+# configurations measured by their own routines (one JSON line each)
+SPECIAL = {
+    "batch_20000": 4,      # 20,000 segments, sizes floor(2^U), U ~ U(8, 20): ~2^31.2 keys
+    "batch_2^28": 4,       # the same seeded list truncated at 2^28 keys in total
+    "serving": 5,          # Poisson request stream, mixed key types, p50/p99 latency
+}
 
 
 def key_bytes(kt: int) -> int:
@@ -91,7 +97,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(SPECIAL))
+    ap.add_argument("--requests", type=int, default=1000, help="serving: requests per load point")
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
     ap.add_argument("--cpu-sample-log2", type=int, default=27)
     ap.add_argument("--trace-file", default=None, help="write the per-kernel table here")
@@ -118,6 +125,11 @@ def main() -> int:
         return 0
 
     from paper_1410_6754_amd import api
+
+    if args.workload.startswith("batch_"):
+        return bench_batch(args)
+    if args.workload == "serving":
+        return bench_serving(args)
 
     n, kt, dist, pay, pkw, cfg = WORKLOADS[args.workload]
     w = key_bytes(kt) + (4 if pay else 0)
@@ -229,6 +241,221 @@ def main() -> int:
     }
     print(json.dumps(line))
     return 0
+
+
+def _log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def _flip64(t):
+    import torch
+    return t.view(torch.int64) ^ torch.iinfo(torch.int64).min
+
+
+def _bits(t):
+    """Signed-integer view of the same bits (for exact comparisons)."""
+    import torch
+    return t.view(torch.int64 if t.element_size() == 8 else torch.int32)
+
+
+def bench_batch(args) -> int:
+    """Configuration 4: thousands of independent uint64 sorts of uneven sizes,
+    one persistent batched call against one call per instance on the same
+    stream (both through the C ABI, same defaults, same output)."""
+    import ctypes
+
+    import torch
+
+    from paper_1410_6754_amd import _lib as L
+    from paper_1410_6754_amd import api
+
+    rng = W.rng_for(SPECIAL[args.workload])
+    sizes = W.batch_sizes(20000, rng, 8, 20)
+    if args.workload == "batch_2^28":
+        sizes = W.truncate_total(sizes, 1 << 28)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    total = int(offs[-1])
+    _log("%s: %d segments, %d keys (2^%.2f); generating" % (args.workload, sizes.size, total,
+                                                         np.log2(total)))
+    keys = W.uniform_u64(total, rng)
+    dev = torch.device("cuda:0")
+    d_keys = torch.from_numpy(keys).to(dev)
+    d_out = torch.empty_like(d_keys)
+    stream = torch.cuda.current_stream()
+    lib = L.lib()
+    s_ptr = stream.cuda_stream
+
+    # one batched call
+    wsb = api.batch_workspace_bytes(W.KEY_U64, offs)
+    ws = api.alloc_workspace(wsb, dev)
+    d_offs = torch.from_numpy(offs.astype(np.int64)).to(dev)
+
+    def batched():
+        api.sort_batch(d_keys, offs, out_keys=d_out, d_offsets=d_offs, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        batched()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_b = (time.perf_counter() - t0) / args.steps
+    ms_b = ev0.elapsed_time(ev1) / args.steps
+    _log("batched: %.3f ms per batch (wall %.3f ms)" % (ms_b, wall_b * 1e3))
+
+    # verify: every segment sorted on the device, sampled segments equal numpy's sort
+    o = _flip64(d_out)
+    bad = o[1:] < o[:-1]
+    cut = torch.from_numpy(offs[1:-1].astype(np.int64) - 1).to(dev)
+    cut = cut[(cut >= 0) & (cut < bad.numel())]
+    bad[cut] = False
+    ok = not bool(bad.any().item())
+    for i in np.linspace(0, sizes.size - 1, 40).astype(int):
+        a, b = int(offs[i]), int(offs[i + 1])
+        ok = ok and np.array_equal(d_out[a:b].cpu().numpy(), np.sort(keys[a:b]))
+
+    # one call per instance through the C ABI, one workspace sized for the largest
+    d_out2 = torch.empty_like(d_keys)
+    wsb1 = api.workspace_bytes(W.KEY_U64, int(sizes.max()))
+    ws1 = api.alloc_workspace(wsb1, dev)
+    kin, kout, wsp = d_keys.data_ptr(), d_out2.data_ptr(), ws1.data_ptr()
+    fn = lib.ams_sort_keys
+    offl = [int(x) for x in offs]
+
+    def per_instance():
+        for i in range(sizes.size):
+            a = offl[i]
+            rc = fn(W.KEY_U64, kin + 8 * a, kout + 8 * a, offl[i + 1] - a, wsp, wsb1, s_ptr, None)
+            if rc != 0:
+                L.check(rc)
+
+    per_instance()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    per_instance()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_p = time.perf_counter() - t0
+    ms_p = ev0.elapsed_time(ev1)
+    same = bool(torch.equal(_bits(d_out), _bits(d_out2)))
+    _log("per instance: %.3f ms (wall %.3f ms); identical output: %s" % (ms_p, wall_p * 1e3, same))
+
+    value = total / (ms_b * 1e-3) / 1e9
+    line = {
+        "metric": "batched sort throughput, GKeys/s (one persistent launch sequence vs one call per instance)",
+        "value": round(value, 3), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_b, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": args.workload, "segments": int(sizes.size), "keys": total,
+                   "sizes": "floor(2^U), U ~ Uniform(8, 20)", "min_size": int(sizes.min()),
+                   "max_size": int(sizes.max()), "median_size": int(np.median(sizes))},
+        "per_instance": {"value": round(total / (ms_p * 1e-3) / 1e9, 3), "unit": "GKeys/s",
+                         "ms": round(ms_p, 3), "host_wall_ms": round(wall_p * 1e3, 3)},
+        "speedup_vs_per_instance": round(ms_p / ms_b, 2),
+        "verified": bool(ok and same),
+    }
+    print(json.dumps(line))
+    return 0 if ok and same else 1
+
+
+def bench_serving(args) -> int:
+    """Configuration 5: a Poisson stream of sort requests (sizes floor(2^U),
+    U ~ U(10, 24); 50% uint64, 25% uint32, 25% float32 N(0,1)) into the
+    serving loop.  Capacity is measured closed-loop (every request queued at
+    once); then the stream is offered at 50%, 80% and 95% of it.  Latency =
+    completion observed by the server - scheduled arrival."""
+    import torch
+
+    from paper_1410_6754_amd import api
+    from paper_1410_6754_amd.server import Server
+
+    rng = W.rng_for(SPECIAL["serving"])
+    nreq = args.requests
+    _, sizes, kts = W.serving_stream(nreq, rng, 1.0, 10, 24)
+    dev = torch.device("cuda:0")
+    _log("serving: %d requests, %d keys; generating" % (nreq, int(sizes.sum())))
+    reqs = []
+    for n, kt in zip(sizes, kts):
+        k = W.keys(int(kt), int(n), rng, "uniform")
+        reqs.append(torch.from_numpy(k).to(dev))
+    torch.cuda.synchronize()
+    total = int(sizes.sum())
+    mean_keys = total / nreq
+
+    def run(rate):
+        """rate None: closed loop.  Returns (latencies_us, span_s)."""
+        with Server(streams=2, max_pending=nreq + 8) as srv:
+            # one warm request of every type
+            for kt in (W.KEY_U64, W.KEY_U32, W.KEY_F32):
+                x = next(r for r, t in zip(reqs, kts) if int(t) == kt)
+                tk = srv.submit(x)
+                srv.wait(tk)
+                srv.release(tk)
+            if rate is None:
+                arr = np.zeros(nreq)
+            else:
+                gaps = np.random.default_rng([W.BASE_SEED + 5, int(rate)]).exponential(1.0 / rate, nreq)
+                arr = np.cumsum(gaps) - gaps[0]
+            tickets, late = [], []
+            t0 = time.perf_counter()
+            for i in range(nreq):
+                while time.perf_counter() - t0 < arr[i]:
+                    pass
+                late.append((time.perf_counter() - t0 - arr[i]) * 1e6)
+                tickets.append(srv.submit(reqs[i]))
+            lat, first, last = [], None, None
+            for i, tk in enumerate(tickets):
+                st = srv.wait(tk)
+                if st["status"] != 0:
+                    raise RuntimeError("request %d failed: %d" % (i, st["status"]))
+                lat.append(st["t_done_us"] - st["t_submit_us"] + late[i])
+                first = st["t_submit_us"] if first is None else min(first, st["t_submit_us"])
+                last = st["t_done_us"] if last is None else max(last, st["t_done_us"])
+                srv.release(tk)
+            return np.array(lat), (last - first) * 1e-6
+
+    lat_c, span_c = run(None)
+    cap = total / span_c
+    _log("capacity (closed loop): %.3f GKeys/s over %.3f s" % (cap / 1e9, span_c))
+    points = []
+    for rho in (0.5, 0.8, 0.95):
+        rate = rho * cap / mean_keys
+        lat, span = run(rate)
+        points.append({"offered": rho, "requests_per_s": round(rate, 1),
+                       "achieved_GKeys_s": round(total / span / 1e9, 3),
+                       "p50_us": round(float(np.percentile(lat, 50)), 1),
+                       "p99_us": round(float(np.percentile(lat, 99)), 1)})
+        _log("offered %.2f: %s" % (rho, points[-1]))
+
+    # spot check: a few results equal the standalone sort
+    ok = True
+    with Server(streams=2) as srv:
+        for i in range(0, nreq, max(1, nreq // 8)):
+            tk = srv.submit(reqs[i])
+            srv.wait(tk)
+            got = srv.result(tk)
+            torch.cuda.synchronize()
+            srv.release(tk)
+            ok = ok and bool(torch.equal(_bits(got), _bits(api.sort_keys(reqs[i]))))
+    line = {
+        "metric": "served sort throughput at capacity, GKeys/s, with p50/p99 latency at 50/80/95% load",
+        "value": round(cap / 1e9, 3), "unit": "GKeys/s", "n_gpus": 1, "steps": nreq, "warmup": 3,
+        "ms_per_step": round(span_c * 1e3 / nreq, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64/u32/f32", "data": "synthetic",
+        "config": {"workload": "serving", "requests": nreq, "keys": total,
+                   "sizes": "floor(2^U), U ~ Uniform(10, 24)", "types": "50% u64, 25% u32, 25% f32"},
+        "closed_loop": {"p50_us": round(float(np.percentile(lat_c, 50)), 1),
+                        "p99_us": round(float(np.percentile(lat_c, 99)), 1)},
+        "load_points": points,
+        "verified": ok,
+    }
+    print(json.dumps(line))
+    return 0 if ok else 1
 
 
 if __name__ == "__main__":

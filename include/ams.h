@@ -192,7 +192,10 @@ ams_status ams_result(ams_server *srv, uint64_t ticket, void **d_keys, uint32_t 
 ams_status ams_result_copy(ams_server *srv, uint64_t ticket, void *d_keys, uint32_t *d_vals,
                            void *stream);
 
-/* Free a finished request's result buffers and forget the ticket. */
+/* Free a finished request's result buffers and forget the ticket.  The
+ * buffers are freed in stream order on a server stream: work of the caller
+ * that reads them (ams_result pointers, an ams_result_copy) must have
+ * completed, e.g. its stream synchronised, before this call. */
 ams_status ams_release(ams_server *srv, uint64_t ticket);
 
 /* Drain outstanding work, free everything. */

@@ -8,15 +8,23 @@
 // with a root table that points at every request's own buffers.  Batches on
 // different streams overlap on the device.  Completion is observed through
 // events; results stay in server-owned device buffers until released.
+//
+// Per batch the host does one plan, one result allocation (carved into every
+// request's buffers, freed when the last of them is released), one workspace
+// allocation and one copy of the root table from a pinned buffer that each
+// stream keeps; the device's default memory pool is set to keep freed memory,
+// so these allocations are served from the pool after the first batches.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "ams.h"
@@ -53,9 +61,25 @@ struct Batch {
   std::vector<uint64_t> tickets;
   void *ws = nullptr;
   size_t ws_bytes = 0;
+};
+
+// One allocation holding the results of a batch's requests.
+struct ResultBlock {
+  void *ptr = nullptr;
+  uint32_t live = 0;  // requests of the batch not yet released
+};
+
+// What each worker stream keeps between batches (one batch per stream at a
+// time, so reuse never races with a copy still in flight).
+struct StreamState {
+  hipStream_t s = nullptr;
+  bool busy = false;
   Root *h_roots = nullptr;  // pinned staging of the root table
+  size_t cap_roots = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 double now_us(const std::chrono::steady_clock::time_point &t0) {
   return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
@@ -70,8 +94,8 @@ struct ams_server {
   size_t budget = 0;
   size_t reserved = 0;  // results of unreleased requests + workspaces of running batches
   uint32_t max_pending = 4096;
-  std::vector<hipStream_t> streams;
-  std::vector<bool> busy;
+  std::vector<StreamState> streams;
+  std::unordered_map<uint64_t, ResultBlock> blocks;  // by batch id
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> queue;  // pending tickets, FIFO
@@ -96,12 +120,21 @@ struct ams_server {
     return r.result_bytes + workspace_for(r.type, r.vals != nullptr, one);
   }
 
+  // Result bytes of a request as carved from its batch's block.
+  static size_t carved(const Request &r) {
+    return align256(r.n * kbytes(r.type)) + (r.vals ? align256(r.n * 4) : 0);
+  }
+
   // Called with mu held.  Forms and launches batches while a stream is free.
+  // A batch takes the oldest pending requests of the head's key type and
+  // payload, in FIFO order, while the result bytes plus a bound on the
+  // workspace fit the budget; the exact plan is made once for the batch and
+  // requests are dropped from its end if it does not fit.
   void schedule() {
     for (;;) {
       int free_s = -1;
       for (size_t i = 0; i < streams.size(); ++i)
-        if (!busy[i]) {
+        if (!streams[i].busy) {
           free_s = (int)i;
           break;
         }
@@ -109,26 +142,33 @@ struct ams_server {
       const Request &head = reqs[queue.front()];
       const ams_key_t type = head.type;
       const bool pay = head.vals != nullptr;
+      const size_t ew = kbytes(type) + (pay ? 4 : 0);
       std::vector<uint64_t> pick, sizes;
-      size_t results = 0, ws = 0;
+      size_t results = 0;
       uint64_t keys = 0;
       for (auto it = queue.begin(); it != queue.end(); ++it) {
         Request &r = reqs[*it];
         if (r.type != type || (r.vals != nullptr) != pay) continue;
         if (!pick.empty() && (keys + r.n > max_batch_keys || pick.size() >= max_batch_reqs)) break;
-        sizes.push_back(r.n);
-        size_t w2 = workspace_for(type, pay, sizes);
-        if (reserved + results + r.result_bytes + w2 > budget) {
-          sizes.pop_back();
-          break;  // keep FIFO order: later requests wait with this one
-        }
+        // workspace bound: the keys once more plus tables (well under the keys
+        // again) and a fixed part per request
+        const size_t bound = 2 * (keys + r.n) * ew + (pick.size() + 1) * 4096 + (64u << 20);
+        if (!pick.empty() && reserved + results + carved(r) + bound > budget) break;
         pick.push_back(*it);
-        results += r.result_bytes;
-        ws = w2;
+        sizes.push_back(r.n);
+        results += carved(r);
         keys += r.n;
       }
+      size_t ws = 0;
+      while (!pick.empty()) {
+        ws = workspace_for(type, pay, sizes);
+        if (ws && reserved + results + ws <= budget) break;
+        results -= carved(reqs[pick.back()]);
+        pick.pop_back();
+        sizes.pop_back();
+      }
       if (pick.empty()) return;  // not enough memory yet; retry when some frees
-      launch(free_s, type, pay, pick, ws, results);
+      launch(free_s, type, pay, pick, sizes, ws, results);
     }
   }
 
@@ -139,72 +179,87 @@ struct ams_server {
     --outstanding;
   }
 
-  void launch(int si, ams_key_t type, bool pay, const std::vector<uint64_t> &pick, size_t ws_bytes,
-              size_t results) {
-    hipStream_t s = streams[si];
+  void launch(int si, ams_key_t type, bool pay, const std::vector<uint64_t> &pick,
+              const std::vector<uint64_t> &sizes, size_t ws_bytes, size_t results) {
+    StreamState &ss = streams[si];
+    hipStream_t s = ss.s;
     Batch b;
     b.id = next_batch++;
     b.stream = si;
     b.tickets = pick;
     b.ws_bytes = ws_bytes;
     const double ta = now_us(t0);
-    for (uint64_t t : pick) {
-      for (auto it = queue.begin(); it != queue.end(); ++it)
-        if (*it == t) {
-          queue.erase(it);
-          break;
+    {
+      const std::unordered_set<uint64_t> taken(pick.begin(), pick.end());
+      size_t k = 0;
+      for (auto it = queue.begin(); it != queue.end() && k < pick.size();) {
+        if (taken.count(*it)) {
+          it = queue.erase(it);
+          ++k;
+        } else {
+          ++it;
         }
+      }
     }
-    // result buffers and workspace, stream-ordered
     ams_status st = AMS_OK;
-    std::vector<uint64_t> sizes;
-    for (uint64_t t : pick) {
-      Request &r = reqs[t];
-      sizes.push_back(r.n);
-      r.st.t_admit_us = ta;
-      r.st.batch_id = b.id;
-      r.st.batch_size = (uint32_t)pick.size();
-      if (hipMallocAsync(&r.out_k, r.n * kbytes(type), s) != hipSuccess) st = AMS_ENOMEM;
-      if (pay && hipMallocAsync((void **)&r.out_v, r.n * 4, s) != hipSuccess) st = AMS_ENOMEM;
-    }
+    ResultBlock blk;
     Plan pl;
-    if (!st) st = make_plan(pl, (int)type, pay, sizes.data(), (uint32_t)sizes.size(), 0, nullptr);
+    st = make_plan(pl, (int)type, pay, sizes.data(), (uint32_t)sizes.size(), 0, nullptr);
+    if (!st && hipMallocAsync(&blk.ptr, results ? results : 256, s) != hipSuccess) st = AMS_ENOMEM;
     if (!st && hipMallocAsync(&b.ws, pl.bytes, s) != hipSuccess) st = AMS_ENOMEM;
-    if (!st && hipHostMalloc((void **)&b.h_roots, sizeof(Root) * pick.size(), 0) != hipSuccess)
-      st = AMS_ENOMEM;
+    if (!st && ss.cap_roots < pick.size()) {
+      if (ss.h_roots) (void)hipHostFree(ss.h_roots);
+      ss.h_roots = nullptr;
+      ss.cap_roots = 0;
+      size_t cap = std::max<size_t>(pick.size(), 1024);
+      if (hipHostMalloc((void **)&ss.h_roots, sizeof(Root) * cap, 0) != hipSuccess) st = AMS_ENOMEM;
+      else ss.cap_roots = cap;
+    }
     if (!st) {
       uint64_t off = 0;
+      char *cur = (char *)blk.ptr;
       for (size_t i = 0; i < pick.size(); ++i) {
         Request &r = reqs[pick[i]];
+        r.out_k = cur;
+        cur += align256(r.n * kbytes(type));
+        r.out_v = nullptr;
+        if (pay) {
+          r.out_v = (uint32_t *)cur;
+          cur += align256(r.n * 4);
+        }
         Root R;
         R.kin = r.keys;
         R.vin = pay ? r.vals : nullptr;
         R.kout = r.out_k;
-        R.vout = pay ? r.out_v : nullptr;
+        R.vout = r.out_v;
         R.n = r.n;
         R.tmp_off = off;
         off += r.n;
-        b.h_roots[i] = R;
+        ss.h_roots[i] = R;
       }
-      if (hipMemcpyAsync((char *)b.ws + pl.o_roots, b.h_roots, sizeof(Root) * pick.size(),
+      if (hipMemcpyAsync((char *)b.ws + pl.o_roots, ss.h_roots, sizeof(Root) * pick.size(),
                          hipMemcpyHostToDevice, s) != hipSuccess)
         st = AMS_EHIP;
     }
-    (void)hipEventCreate(&b.ev0);
-    (void)hipEventCreate(&b.ev1);
     if (!st) {
-      (void)hipEventRecord(b.ev0, s);
+      (void)hipEventRecord(ss.ev0, s);
       RootSource rs;
       memset(&rs, 0, sizeof rs);
       rs.mode = 2;
       st = run_plan_ex(pl, b.ws, rs, s, nullptr, nullptr, nullptr, nullptr, true);
-      (void)hipEventRecord(b.ev1, s);
+      (void)hipEventRecord(ss.ev1, s);
     }
     const double tl = now_us(t0);
+    blk.live = (uint32_t)pick.size();
+    if (blk.ptr) blocks[b.id] = blk;
     reserved += results + ws_bytes;
     for (uint64_t t : pick) {
       Request &r = reqs[t];
+      r.st.t_admit_us = ta;
       r.st.t_launch_us = tl;
+      r.st.batch_id = b.id;
+      r.st.batch_size = (uint32_t)pick.size();
+      r.result_bytes = carved(r);
       if (st) {
         fail(r, st);
       } else {
@@ -218,14 +273,15 @@ struct ams_server {
       cv_done.notify_all();
       return;
     }
-    busy[si] = true;
+    ss.busy = true;
     running.push_back(b);
   }
 
   void finish_batch(Batch &b, bool ok) {
+    StreamState &ss = streams[b.stream];
     if (ok) {
       float ms = 0;
-      (void)hipEventElapsedTime(&ms, b.ev0, b.ev1);
+      (void)hipEventElapsedTime(&ms, ss.ev0, ss.ev1);
       const double td = now_us(t0);
       for (uint64_t t : b.tickets) {
         Request &r = reqs[t];
@@ -237,12 +293,20 @@ struct ams_server {
         --outstanding;
       }
     }
-    if (b.ws) (void)hipFreeAsync(b.ws, streams[b.stream]);
-    if (b.h_roots) (void)hipHostFree(b.h_roots);
-    if (b.ev0) (void)hipEventDestroy(b.ev0);
-    if (b.ev1) (void)hipEventDestroy(b.ev1);
+    if (b.ws) (void)hipFreeAsync(b.ws, ss.s);
     b.ws = nullptr;
-    b.h_roots = nullptr;
+  }
+
+  // One request's results are no longer needed: drop it from its block and
+  // free the block after the last one.
+  void drop_result(Request &r) {
+    auto it = blocks.find(r.st.batch_id);
+    if (it != blocks.end() && --it->second.live == 0) {
+      (void)hipFreeAsync(it->second.ptr, streams[0].s);
+      blocks.erase(it);
+    }
+    r.out_k = nullptr;
+    r.out_v = nullptr;
   }
 
   // Called with mu held: retire finished batches.
@@ -250,7 +314,7 @@ struct ams_server {
     bool any = false;
     for (size_t i = 0; i < running.size();) {
       Batch &b = running[i];
-      hipError_t q = hipEventQuery(b.ev1);
+      hipError_t q = hipEventQuery(streams[b.stream].ev1);
       if (q == hipErrorNotReady) {
         ++i;
         continue;
@@ -263,7 +327,7 @@ struct ams_server {
       }
       finish_batch(b, q == hipSuccess);
       reserved -= b.ws_bytes;
-      busy[b.stream] = false;
+      streams[b.stream].busy = false;
       running.erase(running.begin() + i);
       any = true;
     }
@@ -312,17 +376,29 @@ ams_server *ams_server_create(int device, size_t hbm_budget, uint32_t max_pendin
   s->budget = hbm_budget;
   s->max_pending = max_pending ? max_pending : 4096;
   uint32_t ns = n_streams ? n_streams : 2;
+  // keep freed memory in the device's default pool (result blocks and
+  // workspaces come and go with every batch)
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   for (uint32_t i = 0; i < ns; ++i) {
-    hipStream_t h;
-    if (hipStreamCreateWithFlags(&h, hipStreamNonBlocking) != hipSuccess) {
-      set_error("hipStreamCreate failed");
+    StreamState ss;
+    if (hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&ss.ev0) != hipSuccess || hipEventCreate(&ss.ev1) != hipSuccess) {
+      set_error("hipStreamCreate / hipEventCreate failed");
       if (st) *st = AMS_EHIP;
-      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      s->streams.push_back(ss);
+      for (StreamState &x : s->streams) {
+        if (x.s) (void)hipStreamDestroy(x.s);
+        if (x.ev0) (void)hipEventDestroy(x.ev0);
+        if (x.ev1) (void)hipEventDestroy(x.ev1);
+      }
       delete s;
       return nullptr;
     }
-    s->streams.push_back(h);
-    s->busy.push_back(false);
+    s->streams.push_back(ss);
   }
   s->worker = std::thread([s] { s->loop(); });
   return s;
@@ -421,10 +497,10 @@ ams_status ams_release(ams_server *srv, uint64_t ticket) {
     set_error("request %llu has not finished", (unsigned long long)ticket);
     return AMS_EAGAIN;
   }
-  hipStream_t s = srv->streams[0];
-  if (r.out_k) (void)hipFreeAsync(r.out_k, s);
-  if (r.out_v) (void)hipFreeAsync(r.out_v, s);
-  if (r.st.batch_id) srv->reserved -= r.result_bytes;
+  if (r.st.batch_id) {
+    srv->drop_result(r);
+    srv->reserved -= r.result_bytes;
+  }
   srv->reqs.erase(it);
   srv->cv_work.notify_one();
   return AMS_OK;
@@ -441,13 +517,14 @@ void ams_server_destroy(ams_server *srv) {
   }
   srv->cv_work.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
-  for (auto &kv : srv->reqs) {
-    if (kv.second.out_k) (void)hipFreeAsync(kv.second.out_k, srv->streams[0]);
-    if (kv.second.out_v) (void)hipFreeAsync(kv.second.out_v, srv->streams[0]);
-  }
-  for (hipStream_t s : srv->streams) {
-    (void)hipStreamSynchronize(s);
-    (void)hipStreamDestroy(s);
+  for (auto &kv : srv->blocks) (void)hipFreeAsync(kv.second.ptr, srv->streams[0].s);
+  srv->blocks.clear();
+  for (StreamState &x : srv->streams) {
+    (void)hipStreamSynchronize(x.s);
+    (void)hipStreamDestroy(x.s);
+    if (x.h_roots) (void)hipHostFree(x.h_roots);
+    (void)hipEventDestroy(x.ev0);
+    (void)hipEventDestroy(x.ev1);
   }
   delete srv;
 }

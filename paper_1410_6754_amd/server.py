@@ -70,6 +70,10 @@ class Server:
         return k.value, v.value
 
     def release(self, ticket: int):
+        # the result may still be read by work queued on the current stream
+        # (result() copies there); the library frees in order on its own
+        # stream, so let that work finish first
+        torch.cuda.current_stream(self.device).synchronize()
         check(lib().ams_release(self._h, ticket))
         self._keep.pop(ticket, None)
 
