@@ -80,16 +80,50 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(keys: np.ndarray, kt: int, vals, sample_n: int):
+def host_threads() -> int:
+    """Host threads this process may use: its CPU affinity, capped by the
+    share OMP_NUM_THREADS names when set."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(keys: np.ndarray, kt: int, vals, sample_n: int, single_n: int):
+    """The oracle's mergesort timed on the host: the plain parallel form on
+    all host threads over the first sample_n keys (the reported value), and
+    the single-threaded form over the first single_n keys."""
     import oracle
+    threads = host_threads()
     sample = np.ascontiguousarray(keys[:sample_n])
-    sv = None if vals is None else np.ascontiguousarray(vals[:sample_n])
     t0 = time.perf_counter()
-    oracle.oracle_sort(kt, sample, sv)
+    oracle.oracle_sort_perm_parallel(kt, sample, threads)
     dt = time.perf_counter() - t0
-    return {"value": sample_n / dt / 1e9, "unit": "GKeys/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d keys of the workload (2^%d), one call of the oracle's "
-                      "textbook mergesort, single-threaded, %.2f s" % (sample_n, int(np.log2(sample_n)), dt)}
+    single = np.ascontiguousarray(keys[:single_n])
+    sv = None if vals is None else np.ascontiguousarray(vals[:single_n])
+    t1 = time.perf_counter()
+    oracle.oracle_sort(kt, single, sv)
+    dt1 = time.perf_counter() - t1
+    return {"value": sample_n / dt / 1e9, "unit": "GKeys/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d keys of the workload (2^%d), one call of the oracle's plain "
+                      "parallel mergesort (per-thread chunks, then a pairwise merge tree) on %d "
+                      "host threads, %.2f s" % (sample_n, int(np.log2(sample_n)), threads, dt),
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": single_n / dt1 / 1e9, "unit": "GKeys/s", "cores": 1,
+                              "sample": "first %d keys (2^%d), the textbook mergesort, %.2f s"
+                                        % (single_n, int(np.log2(single_n)), dt1)}}
 
 
 def main() -> int:
@@ -100,7 +134,10 @@ def main() -> int:
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(SPECIAL))
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per load point")
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
-    ap.add_argument("--cpu-sample-log2", type=int, default=27)
+    ap.add_argument("--cpu-sample-log2", type=int, default=27,
+                    help="keys the parallel oracle sorts (log2)")
+    ap.add_argument("--cpu-single-log2", type=int, default=25,
+                    help="keys the single-threaded oracle sorts (log2)")
     ap.add_argument("--trace-file", default=None, help="write the per-kernel table here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy three times (the known-size "
@@ -214,8 +251,10 @@ def main() -> int:
     cpu = None
     if not args.no_cpu:
         sample_n = min(n, 1 << args.cpu_sample_log2)
-        print("bench: timing the oracle on %d keys" % sample_n, file=sys.stderr, flush=True)
-        cpu = cpu_baseline(keys, kt, vals, sample_n)
+        single_n = min(n, 1 << args.cpu_single_log2)
+        print("bench: timing the oracle on %d keys (%d threads) and %d keys (1 thread)"
+              % (sample_n, host_threads(), single_n), file=sys.stderr, flush=True)
+        cpu = cpu_baseline(keys, kt, vals, sample_n, single_n)
 
     value = n / (ms_per_step * 1e-3) / 1e9
     line = {

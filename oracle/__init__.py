@@ -36,5 +36,6 @@ from .sort import (  # noqa: F401
     ord_keys,
     oracle_sort,
     oracle_sort_perm,
+    oracle_sort_perm_parallel,
     py_mergesort_perm,
 )

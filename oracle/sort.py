@@ -12,6 +12,9 @@ ord is the identity for unsigned integers.  Float32 keys are ordered by IEEE
 
 Three independent routes compute pi:
   * ``oracle_sort_perm``  textbook top-down mergesort in C (``mergesort.c``);
+    ``oracle_sort_perm_parallel`` is the same mergesort on several threads
+    (chunks, then a pairwise merge tree), used to time the oracle on all
+    host cores;
   * ``py_mergesort_perm`` the same textbook algorithm in pure Python, for
     tiny inputs;
   * ``brute_force_perm``  enumeration of all n! permutations, keeping the one
@@ -46,7 +49,8 @@ def build_oracle(force: bool = False) -> str:
     """Compile ``mergesort.c`` with gcc into ``_liboracle.so`` (plain C)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", _SRC, "-o", tmp])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-pthread", "-shared", "-fPIC", _SRC,
+                               "-o", tmp])
         os.replace(tmp, _SO)
     return _SO
 
@@ -61,6 +65,9 @@ def _load():
         lib.oracle_sort.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_sort.restype = ctypes.c_int
+        lib.oracle_sort_perm_parallel.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64,
+                                                  ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_sort_perm_parallel.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -109,6 +116,20 @@ def oracle_sort_perm(key_type: int, keys: np.ndarray) -> np.ndarray:
         rc = _load().oracle_sort_perm(key_type, keys.ctypes.data, n, perm.ctypes.data)
         if rc:
             raise MemoryError("oracle_sort_perm failed (%d)" % rc)
+    return perm
+
+
+def oracle_sort_perm_parallel(key_type: int, keys: np.ndarray, threads: int) -> np.ndarray:
+    """pi from the plain parallel mergesort (one chunk per thread, then a
+    pairwise merge tree); the same permutation as ``oracle_sort_perm``."""
+    keys = np.ascontiguousarray(keys, dtype=key_dtype(key_type))
+    n = keys.size
+    perm = np.empty(n, dtype=np.uint64)
+    if n:
+        rc = _load().oracle_sort_perm_parallel(key_type, keys.ctypes.data, n, perm.ctypes.data,
+                                               int(threads))
+        if rc:
+            raise ValueError("oracle_sort_perm_parallel failed (%d)" % rc)
     return perm
 
 

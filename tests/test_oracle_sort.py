@@ -157,3 +157,20 @@ def test_fingerprint_float_bits():
     a = np.array([0x80000000, 0x00000000], dtype=np.uint32).view(np.float32)
     b = np.array([0x00000000, 0x00000000], dtype=np.uint32).view(np.float32)
     assert checkers.fingerprint(KEY_F32, a) != checkers.fingerprint(KEY_F32, b)
+
+
+@pytest.mark.parametrize("key_type", [KEY_U32, KEY_U64, KEY_F32])
+def test_parallel_mergesort_matches_stable_definition(key_type):
+    # the plain parallel form (chunks + pairwise merge tree) must give the same
+    # unique permutation: numpy's stable argsort of ord (value, then position)
+    rng = np.random.default_rng(6)
+    for n in [1, 2, 3, 7, 1000, 65537]:
+        if key_type == KEY_F32:
+            keys = rng.standard_normal(n).astype(np.float32)
+            keys[rng.integers(0, n, size=max(1, n // 4))] = 0.0
+        else:
+            keys = rng.integers(0, 40, size=n).astype(oracle.key_dtype(key_type))
+        want = np.argsort(oracle.ord_keys(key_type, keys), kind="stable")
+        for threads in [1, 2, 3, 5, 8, 16]:
+            perm = oracle.oracle_sort_perm_parallel(key_type, keys, threads)
+            assert np.array_equal(perm.astype(np.int64), want), (n, threads)
