@@ -95,6 +95,48 @@ AMS_DEV uint32_t draw_pos(uint64_t state, uint32_t i, uint32_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// Raw buffer access.  A buffer resource covers [base, base + bytes); loads
+// outside it return zero instead of faulting, which lets ragged tails load
+// with full-width instructions.  The resource and the byte offsets are
+// wave-uniform (scalar registers); each lane adds its own offset.
+// ---------------------------------------------------------------------------
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+AMS_DEV Rsrc make_rsrc(const void *base, uint32_t bytes) {
+  // word 3: raw (untyped) access with 32-bit data format, as gfx9 expects
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
+// 16 bytes per lane: 2 uint64 or 4 uint32 keys.
+template <typename K> struct Vec16;
+template <> struct Vec16<uint64_t> {
+  static constexpr uint32_t N = 2;
+  static AMS_DEV void get(v4u32 v, uint64_t *x) {
+    x[0] = ((uint64_t)v.y << 32) | v.x;
+    x[1] = ((uint64_t)v.w << 32) | v.z;
+  }
+};
+template <> struct Vec16<uint32_t> {
+  static constexpr uint32_t N = 4;
+  static AMS_DEV void get(v4u32 v, uint32_t *x) {
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+    x[3] = v.w;
+  }
+};
+
+// Wave-uniform copy of a pointer (scalar registers).
+template <typename T> AMS_DEV T *uniform_ptr(T *p) {
+  const uint64_t a = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return (T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
+// ---------------------------------------------------------------------------
 // Wavefront primitives (wave64).
 // ---------------------------------------------------------------------------
 AMS_DEV uint32_t lane_id() { return __lane_id(); }

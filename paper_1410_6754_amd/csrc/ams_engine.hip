@@ -391,12 +391,16 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
     const bool enc = buf == BUF_IN;
     uint32_t lo = t * lv.TC;
     uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
+    // the tile through a buffer resource: 16-byte loads, zeros past its end
+    const Rsrc rs = make_rsrc(uniform_ptr(src + lo), (hi - lo) * (uint32_t)sizeof(K));
+    constexpr uint32_t V = Vec16<K>::N;
     for (uint32_t base = lo; base < hi; base += 256 * CU) {
       K xs[CU];
 #pragma unroll
-      for (int u = 0; u < CU; ++u) {
-        uint32_t p = base + u * 256 + tid;
-        xs[u] = p < hi ? src[p] : (K)0;
+      for (uint32_t k = 0; k < CU / V; ++k) {
+        const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(
+            rs, tid * 16u, (base - lo) * (uint32_t)sizeof(K) + k * (256u * 16u), 0);
+        Vec16<K>::get(v, &xs[k * V]);
       }
       if (enc) {
 #pragma unroll
@@ -405,8 +409,8 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
       uint32_t ids[CU];
       classify_batch<K, CU>(xs, ids, sTree, sSpl, logm, eq);
 #pragma unroll
-      for (int u = 0; u < CU; ++u) {
-        uint32_t p = base + u * 256 + tid;
+      for (uint32_t u = 0; u < CU; ++u) {
+        const uint32_t p = base + (u / V) * (V * 256u) + V * tid + (u % V);
         if (p < hi) atomicAdd(&sH[ids[u]], 1u);
       }
     }
@@ -978,15 +982,27 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
 // their order inside a child is immaterial and a chunk is regrouped with LDS
 // atomics instead of ballot ranks.  The next chunk's keys are loaded into
 // registers while the current one is classified, regrouped and written.
-constexpr uint32_t SCK_THREADS = 512;
+constexpr uint32_t SCK_THREADS = 1024;
+
+// Chunk keys of a tile: the tile's keys are read through a buffer resource
+// over [tile start, tile end), 16 bytes per lane and load; chunk offset coff
+// is in bytes from the tile start.  Key u of a thread sits at chunk position
+// sck_pos(u) (positions past the tile end read as zero).
+template <typename K, int KPT> AMS_DEV uint32_t sck_pos(uint32_t u) {
+  constexpr uint32_t V = Vec16<K>::N;
+  return (u / V) * (V * SCK_THREADS) + V * threadIdx.x + (u % V);
+}
 
 template <int KT, int KPT>
-AMS_DEV void sck_load(const typename Key<KT>::T *src, uint32_t cb, uint32_t hi,
-                      typename Key<KT>::T (&x)[KPT]) {
+AMS_DEV void sck_load(Rsrc rs, uint32_t coff, typename Key<KT>::T (&x)[KPT]) {
+  typedef typename Key<KT>::T K;
+  constexpr uint32_t V = Vec16<K>::N;
+  static_assert(KPT % V == 0, "whole 16-byte loads per thread");
 #pragma unroll
-  for (int k = 0; k < KPT; ++k) {
-    const uint32_t p = cb + threadIdx.x + SCK_THREADS * k;
-    x[k] = p < hi ? src[p] : (typename Key<KT>::T)0;
+  for (uint32_t k = 0; k < KPT / V; ++k) {
+    const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(rs, threadIdx.x * 16u,
+                                                          coff + k * (SCK_THREADS * 16u), 0);
+    Vec16<K>::get(v, &x[k * V]);
   }
 }
 
@@ -1015,8 +1031,21 @@ AMS_DEV void block_exscan_to(const uint32_t *in, uint32_t *out, uint32_t n, uint
   __syncthreads();
 }
 
+// Buffer resource over the keys of tile g of a level (wave-uniform).
+template <typename K>
+AMS_DEV Rsrc tile_rsrc(const Ws &w, const Lev &lv, uint32_t P, uint32_t g) {
+  const uint32_t i = find_owner(w.tileStart, P, g);
+  const uint32_t t = g - w.tileStart[i];
+  const Seg s = w.act[lv.level][i];
+  const Root R = w.roots[s.root];
+  const uint32_t lo = t * lv.TC;
+  const uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
+  const K *src = kptr<K>(w, R, seg_buf(s.meta)) + s.off + lo;
+  return make_rsrc(uniform_ptr(src), __builtin_amdgcn_readfirstlane((hi - lo) * (uint32_t)sizeof(K)));
+}
+
 template <int KT, int KPT>
-__global__ void __launch_bounds__(SCK_THREADS, 4) k_scatter_keys(Ws w, Lev lv) {
+__global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
   typedef typename Key<KT>::T K;
   constexpr uint32_t CHK = SCK_THREADS * KPT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1038,6 +1067,11 @@ __global__ void __launch_bounds__(SCK_THREADS, 4) k_scatter_keys(Ws w, Lev lv) {
   bool eq = false;
   const K *gSpl = nullptr;
   for (uint32_t c = tid; c < CH; c += SCK_THREADS) sCnt[c] = 0;
+  if (ir.first >= ir.end) return;
+  // The keys of the first chunk of a tile are loaded while the previous
+  // tile's last chunk is processed, so no tile starts on an empty pipeline.
+  K xa[KPT];
+  sck_load<KT, KPT>(tile_rsrc<K>(w, lv, P, ir.first), 0u, xa);
   for (uint32_t g = ir.first; g < ir.end; g += ir.step) {
     const uint32_t i = find_owner(w.tileStart, P, g);
     const uint32_t t = g - w.tileStart[i];
@@ -1048,8 +1082,9 @@ __global__ void __launch_bounds__(SCK_THREADS, 4) k_scatter_keys(Ws w, Lev lv) {
     const bool enc = buf == BUF_IN;
     const uint32_t lo = t * lv.TC;
     const uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
-    K xa[KPT];
-    sck_load<KT, KPT>(src, lo, hi, xa);  // in flight while the tables load
+    const bool more = g + ir.step < ir.end;
+    const Rsrc rs = make_rsrc(uniform_ptr(src + lo), (hi - lo) * (uint32_t)sizeof(K));
+    const Rsrc rsn = more ? tile_rsrc<K>(w, lv, P, g + ir.step) : rs;
     if (i != cur) {
       __syncthreads();
       logm = meta_logm(s.meta);
@@ -1072,7 +1107,8 @@ __global__ void __launch_bounds__(SCK_THREADS, 4) k_scatter_keys(Ws w, Lev lv) {
     __syncthreads();
     for (uint32_t cb = lo; cb < hi; cb += CHK) {
       K xb[KPT];
-      if (cb + CHK < hi) sck_load<KT, KPT>(src, cb + CHK, hi, xb);
+      if (cb + CHK < hi) sck_load<KT, KPT>(rs, (cb + CHK - lo) * (uint32_t)sizeof(K), xb);
+      else if (more) sck_load<KT, KPT>(rsn, 0u, xb);
       if (enc) {
 #pragma unroll
         for (int k = 0; k < KPT; ++k) xa[k] = Key<KT>::enc(xa[k]);
@@ -1081,7 +1117,7 @@ __global__ void __launch_bounds__(SCK_THREADS, 4) k_scatter_keys(Ws w, Lev lv) {
       classify_batch<K, KPT>(xa, xcs, sTree, gSpl, logm, eq);
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
-        const uint32_t p = cb + tid + SCK_THREADS * k;
+        const uint32_t p = cb + sck_pos<K, KPT>(k);
         uint32_t c = 0, slot = 0;
         if (p < hi) {
           c = sI2C[xcs[k]];
@@ -1108,7 +1144,7 @@ __global__ void __launch_bounds__(SCK_THREADS, 4) k_scatter_keys(Ws w, Lev lv) {
       }
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
-        const uint32_t p = cb + tid + SCK_THREADS * k;
+        const uint32_t p = cb + sck_pos<K, KPT>(k);
         if (p < hi) {
           const uint32_t c = xcs[k] >> 16;
           const uint32_t q = sL[c] + (xcs[k] & 0xFFFFu);
@@ -1302,6 +1338,10 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     while (f < need && f < FMAX) f <<= 1;
   }
   const uint32_t logf = ilog2c(f);
+  // placed-position bitmap: position p is bit p / nwb of word p % nwb, so
+  // neighbouring positions fall in different words (C <= 32 * nwb)
+  constexpr uint32_t nwb = CMAX / 32;
+  static_assert(nwb <= 2 * FMAX, "the bitmap lives in the bucket-counter area");
   static_assert(2 * FMAX == FIN_THREADS, "one bucket counter per thread");
   if (!PAY) sm.cnt[tid] = 0;  // keys-only bucket counters (the previous call ended on a barrier)
   const K *spl = sm.srt + 1;  // spl[b] = splitter just above bucket b
@@ -1438,7 +1478,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         sm.bid[q] = (uint8_t)(eq ? id >> 1 : id);
       }
     }
-    for (uint32_t w32 = tid; w32 < (C + 31) / 32; w32 += FIN_THREADS) sm.bm[w32] = 0;
+    for (uint32_t w32 = tid; w32 < nwb; w32 += FIN_THREADS) sm.bm[w32] = 0;
     if (s + Lb + 8 <= C + FIN_PAD)
       for (uint32_t q = s + tid; q < s + Lb + 8; q += FIN_THREADS) sm.B[q] = (K)~(K)0;
   } else {
@@ -1567,23 +1607,50 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       }
     }
     if (valid) {
-      uint32_t pos = isEq ? q : bs + rk;
+      const uint32_t pos = isEq ? q : bs + rk;
       const K out = dec_out ? Key<KT>::dec(x) : x;
-      if (!PAY && !isEq && padded) {
-        // keys sharing a rank are equal bits: the first claims the rank,
-        // the others claim the empty positions right after it (the masked
-        // path ranks with the position tie-break, so its ranks are unique)
-        uint32_t old = atomicOr(&sm.bm[pos >> 5], 1u << (pos & 31u));
-        while (old & (1u << (pos & 31u))) {
-          ++pos;
-          old = atomicOr(&sm.bm[pos >> 5], 1u << (pos & 31u));
-        }
-      }
+      // keys-only: equal keys share a rank, so they all land on its first
+      // position; every written position is marked (no return value, so the
+      // store does not wait) and the positions left empty are filled below;
+      // a wavefront's marks hit different words and do not serialise
+      if (!PAY) atomicOr(&sm.bm[pos % nwb], 1u << (pos / nwb));
       dst[pos] = out;
       if (PAY) vdst[pos] = v;
     }
   }
   __syncthreads();
+  if (!PAY) {
+    // An empty position p follows a run of equal keys of rank r < p - bs in
+    // its bucket; it receives the bucket's element of rank p - bs, the key x
+    // with #{y < x} <= p - bs < #{y <= x}, found by comparing all pairs.
+    for (uint32_t wi = tid; wi < nwb; wi += FIN_THREADS) {
+      // bits b of word wi with b * nwb + wi < s
+      const uint32_t nb = wi < s ? (s - wi + nwb - 1) / nwb : 0u;
+      const uint32_t full = nb >= 32 ? 0xFFFFFFFFu : (1u << nb) - 1u;
+      uint32_t holes = full & ~sm.bm[wi];
+      while (holes) {
+        const uint32_t p = (uint32_t)__builtin_ctz(holes) * nwb + wi;
+        holes &= holes - 1u;
+        const uint32_t b = sm.bid[p];
+        const uint32_t id = eq ? 2 * b : b;
+        const uint32_t bs = sm.bstart[id], be = sm.bstart[id + 1], k = p - bs;
+        for (uint32_t j = bs; j < be; ++j) {
+          const K x = sm.B[j];
+          uint32_t lt = 0, le = 0;
+          for (uint32_t jj = bs; jj < be; ++jj) {
+            const K y = sm.B[jj];
+            lt += (uint32_t)(y < x);
+            le += (uint32_t)(y <= x);
+          }
+          if (lt <= k && k < le) {
+            dst[p] = dec_out ? Key<KT>::dec(x) : x;
+            break;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // Stable merge of sorted A[0..na) and B[0..nb) (A first on ties) into out,
