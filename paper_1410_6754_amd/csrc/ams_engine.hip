@@ -424,8 +424,11 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
 
 __global__ void __launch_bounds__(256) k_block_reduce(Ws w, Lev lv) {
   const uint32_t tid = threadIdx.x;
-  const uint32_t P = w.ctr->P, total = w.ctr->nblk;
-  for (uint32_t B = blockIdx.x; B < total; B += gridDim.x) {
+  const uint32_t P = w.ctr->P;
+  // item = (tile block, 256 bucket ids)
+  const uint32_t chunks = (lv.HS + 255) / 256, total = w.ctr->nblk * chunks;
+  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const uint32_t B = item / chunks, ch = item - B * chunks;
     uint32_t i = find_owner(w.blkStart, P, B);
     uint32_t bb = B - w.blkStart[i];
     uint32_t t0 = w.tileStart[i] + bb * lv.TB;
@@ -433,9 +436,20 @@ __global__ void __launch_bounds__(256) k_block_reduce(Ws w, Lev lv) {
     Seg s = w.act[lv.level][i];
     uint32_t m = 1u << meta_logm(s.meta);
     uint32_t NB = w.eqOn[i] ? 2 * m - 1 : m;
-    for (uint32_t id = tid; id < NB; id += 256) {
+    const uint32_t id = ch * 256 + tid;
+    if (id < NB) {
+      // 16 tile rows in flight at a time
       uint32_t sum = 0;
-      for (uint32_t t = t0; t < t1; ++t) sum += w.hist[(size_t)t * lv.HS + id];
+      const uint32_t *h = w.hist + (size_t)t0 * lv.HS + id;
+      uint32_t t = t0;
+      for (; t + 16 <= t1; t += 16, h += 16 * (size_t)lv.HS) {
+        uint32_t v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = h[(size_t)u * lv.HS];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) sum += v[u];
+      }
+      for (; t < t1; ++t, h += lv.HS) sum += *h;
       w.blkHist[(size_t)B * lv.HS + id] = sum;
     }
   }
@@ -808,8 +822,11 @@ __global__ void __launch_bounds__(256) k_pack_only(const uint32_t *wgt, uint32_t
 
 __global__ void __launch_bounds__(256) k_tile_scan(Ws w, Lev lv) {
   const uint32_t tid = threadIdx.x;
-  const uint32_t P = w.ctr->P, total = w.ctr->nblk;
-  for (uint32_t B = blockIdx.x; B < total; B += gridDim.x) {
+  const uint32_t P = w.ctr->P;
+  // item = (tile block, 256 children)
+  const uint32_t chunks = (lv.CH + 255) / 256, total = w.ctr->nblk * chunks;
+  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const uint32_t B = item / chunks, ch = item - B * chunks;
     uint32_t i = find_owner(w.blkStart, P, B);
     uint32_t bb = B - w.blkStart[i];
     uint32_t t0 = w.tileStart[i] + bb * lv.TB;
@@ -818,11 +835,30 @@ __global__ void __launch_bounds__(256) k_tile_scan(Ws w, Lev lv) {
     const uint16_t *tf = w.cfirst + (size_t)i * (lv.CH + 1);
     const uint32_t *cs = w.cstart + (size_t)i * (lv.CH + 1);
     const uint32_t *pre = w.blkHist + (size_t)B * lv.HS;  // prefix over earlier blocks
-    for (uint32_t c = tid; c < nch; c += 256) {
+    const uint32_t c = ch * 256 + tid;
+    if (c < nch) {
       const uint32_t f = tf[c], e = tf[c + 1];
       uint32_t run = cs[c];
       for (uint32_t id = f; id < e; ++id) run += pre[id];
-      for (uint32_t t = t0; t < t1; ++t) {
+      // the child's count in 8 tiles at a time (independent loads), then
+      // the running offsets
+      uint32_t t = t0;
+      for (; t + 8 <= t1; t += 8) {
+        uint32_t cnt[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t *h = w.hist + (size_t)(t + u) * lv.HS;
+          uint32_t x = 0;
+          for (uint32_t id = f; id < e; ++id) x += h[id];
+          cnt[u] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          w.tileOff[(size_t)(t + u) * lv.CH + c] = run;
+          run += cnt[u];
+        }
+      }
+      for (; t < t1; ++t) {
         w.tileOff[(size_t)t * lv.CH + c] = run;
         const uint32_t *h = w.hist + (size_t)t * lv.HS;
         for (uint32_t id = f; id < e; ++id) run += h[id];
@@ -1475,10 +1511,8 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         const uint32_t id = xir[k] >> 16;
         const uint32_t q = sm.bstart[id] + (xir[k] & 0xFFFFu);
         sm.B[q] = xk[k];
-        sm.bid[q] = (uint8_t)(eq ? id >> 1 : id);
       }
     }
-    for (uint32_t w32 = tid; w32 < nwb; w32 += FIN_THREADS) sm.bm[w32] = 0;
     if (s + Lb + 8 <= C + FIN_PAD)
       for (uint32_t q = s + tid; q < s + Lb + 8; q += FIN_THREADS) sm.B[q] = (K)~(K)0;
   } else {
@@ -1525,7 +1559,6 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         const uint32_t id = xir[k] >> 16;
         const uint32_t q = sm.cnt[wave * NB + id] + (xir[k] & 0xFFFFu);
         sm.B[q] = xk[k];
-        sm.bid[q] = (uint8_t)(eq ? id >> 1 : id);
         sm.vB[q] = xv[k];
       }
     }
@@ -1545,24 +1578,74 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   __syncthreads();
   // scans of at most Lb + 7 slots past a bucket start stay inside B
   const bool padded = s + Lb + 8 <= C + FIN_PAD;
+  // ---- work order.  A wavefront ranks its keys in a common trip count,
+  // the longest bucket among its lanes, so the keys are handed to lanes
+  // bucket by bucket in order of decreasing bucket size (64 size classes,
+  // counting sort): a wavefront then holds buckets of about one size.
+  // Equality buckets come last; their keys are not ranked.  Lane slot p
+  // belongs to bucket id map(p) and holds the key at B position
+  // bstart[id] + p - lofs[id].
+  uint16_t *lofs = PAY ? (uint16_t *)sm.cnt : (uint16_t *)(sm.cnt + nwb);  // NB first slots
+  uint32_t *hist = (uint32_t *)sm.srt;  // 64 class counters, then the start of equality slots
+  {
+    if (tid < 64) hist[tid] = 0;
+    __syncthreads();
+    const bool haveId = tid < NB;
+    const bool eqId = eq && (tid & 1u);
+    uint32_t L = 0, cls = 0, slot = 0;
+    if (haveId) {
+      L = sm.bstart[tid + 1] - sm.bstart[tid];
+      cls = 63u - (L < 63u ? L : 63u);
+      if (!eqId) slot = atomicAdd(&hist[cls], 1u);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const uint32_t c = hist[lane];
+      hist[lane] = wave_incl_scan(c) - c;
+    }
+    __syncthreads();
+    // order: regular ids by class, then the equality ids (odd ids) in order
+    const uint32_t ord = eqId ? f + (tid >> 1) : hist[cls] + slot;
+    uint32_t *sc = sm.cnt;  // NB words: key counts in work order, then their scan
+    if (haveId) sc[ord] = L;
+    __syncthreads();
+    block_exscan<FIN_THREADS>(sc, NB, sm.wred);
+    const uint32_t lo = haveId ? sc[ord] : 0u;
+    const uint32_t eqStart = eq ? sc[f] : s;
+    __syncthreads();
+    if (tid == 0) hist[64] = eqStart;
+    if (haveId) {
+      lofs[tid] = (uint16_t)lo;
+      const uint32_t bb = eq ? tid >> 1 : tid, word = bb * 0x01010101u;
+      uint32_t j = lo;
+      const uint32_t hi = lo + L;
+      for (; j < hi && (j & 3u); ++j) sm.bid[j] = (uint8_t)bb;
+      for (; j + 4 <= hi; j += 4) *(uint32_t *)(sm.bid + j) = word;
+      for (; j < hi; ++j) sm.bid[j] = (uint8_t)bb;
+    }
+    if (!PAY)
+      for (uint32_t w32 = tid; w32 < nwb; w32 += FIN_THREADS) sm.bm[w32] = 0;
+    __syncthreads();
+  }
+  const uint32_t eqStart = hist[64];
   // ---- all-pairs rank inside every bucket, one slot of FIN_THREADS keys
-  // per pass; a wave's lanes run a common trip count (the longest bucket
-  // among them).  B is not modified while ranking, so every key goes
-  // straight to its final position in dst once its rank is known.
+  // per pass.  B is not modified while ranking, so every key goes straight
+  // to its final position in dst once its rank is known.
 #pragma unroll 1
   for (uint32_t k = 0; k < FIN_KPT; ++k) {
     if (FIN_THREADS * k >= s) break;  // uniform: no key in this or later slots
-    const uint32_t q = tid + FIN_THREADS * k;
-    const bool valid = q < s;
-    const uint32_t qs = valid ? q : 0u;
-    const K x = sm.B[qs];
-    const uint32_t b = sm.bid[qs];
-    const uint32_t id = eq ? 2 * b + ((b + 1 < f && x == spl[b]) ? 1u : 0u) : b;
-    const uint32_t bs = valid ? sm.bstart[id] : 0u;
-    const uint32_t be = valid ? sm.bstart[id + 1] : 0u;
-    const bool isEq = eq && (id & 1u);  // equal keys: any arrangement is final
+    const uint32_t ps = tid + FIN_THREADS * k;
+    const bool valid = ps < s;
+    const uint32_t pv = valid ? ps : 0u;
+    const uint32_t b = sm.bid[pv];
+    const bool isEq = eq && pv >= eqStart;  // equal keys: any arrangement is final
+    const uint32_t id = eq ? 2 * b + (isEq ? 1u : 0u) : b;
+    const uint32_t bs = sm.bstart[id];
+    const uint32_t be = sm.bstart[id + 1];
+    const uint32_t q = bs + pv - lofs[id];
+    const K x = sm.B[q];
     const uint32_t len = (valid && !isEq) ? be - bs : 0u;
-    const uint32_t v = PAY ? sm.vB[qs] : 0u;
+    const uint32_t v = PAY ? sm.vB[q] : 0u;
     // wave-uniform trip count, held in a scalar register
     const uint32_t ml = __builtin_amdgcn_readfirstlane(wave_max(len));
     uint32_t rk = 0;
@@ -1597,7 +1680,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         uint32_t jj[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          jj[u] = d + u < len ? bs + d + u : qs;
+          jj[u] = d + u < len ? bs + d + u : q;
           y[u] = sm.B[jj[u]];
         }
 #pragma unroll
@@ -1631,8 +1714,10 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       while (holes) {
         const uint32_t p = (uint32_t)__builtin_ctz(holes) * nwb + wi;
         holes &= holes - 1u;
-        const uint32_t b = sm.bid[p];
-        const uint32_t id = eq ? 2 * b : b;
+        // the bucket holding position p: the last id whose start is <= p
+        uint32_t id = 0;
+        for (uint32_t span = 1u << ilog2c(NB); span; span >>= 1)
+          if (id + span < NB && sm.bstart[id + span] <= p) id += span;
         const uint32_t bs = sm.bstart[id], be = sm.bstart[id + 1], k = p - bs;
         for (uint32_t j = bs; j < be; ++j) {
           const K x = sm.B[j];
@@ -2132,7 +2217,8 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
     }
     {
       TraceScope ts("block_reduce", l, s);
-      hipLaunchKernelGGL(k_block_reduce, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
+      hipLaunchKernelGGL(k_block_reduce, dim3(grid_for((uint64_t)ls.blocks * ((ls.HS + 255) / 256), 2048)),
+                         dim3(256), 0, s, w, lv);
     }
     {
       TraceScope ts("block_scan", l, s);
@@ -2148,7 +2234,8 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
     }
     {
       TraceScope ts("tile_scan", l, s);
-      hipLaunchKernelGGL(k_tile_scan, dim3(grid_for(ls.blocks, 1024)), dim3(256), 0, s, w, lv);
+      hipLaunchKernelGGL(k_tile_scan, dim3(grid_for((uint64_t)ls.blocks * ((ls.CH + 255) / 256), 2048)),
+                         dim3(256), 0, s, w, lv);
     }
     if (!PAY && (pl.flags & AMS_FLAG_STABLE_PARTITION)) {
       constexpr int KPT = 16;
@@ -2170,14 +2257,23 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
       hipLaunchKernelGGL((k_scatter<KT, true, KPT>), dim3(grid_for(ls.tiles, 512)), dim3(256),
                          ldsS, s, w, lv);
     } else {
-      constexpr int KPT = 8;
-      constexpr uint32_t CHK = SCK_THREADS * KPT;
-      size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + (size_t)ls.CH * 8 + CHK * 2 +
-                    (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + SCK_THREADS / 64 * 4 + ls.CH + 64;
-      allow_lds(k_scatter_keys<KT, KPT>, ldsS);
+      // chunks of 8192 keys, or 4096 when the tables of a wide level
+      // (large k * b) leave too little LDS for the larger staging area
+      auto lds_keys = [&](uint32_t kpt) {
+        const size_t chk = (size_t)SCK_THREADS * kpt;
+        return (size_t)ls.mmax * sizeof(K) + chk * sizeof(K) + (size_t)ls.CH * 8 + chk * 2 +
+               (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + SCK_THREADS / 64 * 4 + ls.CH + 64;
+      };
       TraceScope ts("scatter", l, s);
-      hipLaunchKernelGGL((k_scatter_keys<KT, KPT>), dim3(grid_for(ls.tiles, 512)),
-                         dim3(SCK_THREADS), ldsS, s, w, lv);
+      if (lds_keys(8) <= 163840) {
+        allow_lds(k_scatter_keys<KT, 8>, lds_keys(8));
+        hipLaunchKernelGGL((k_scatter_keys<KT, 8>), dim3(grid_for(ls.tiles, 512)),
+                           dim3(SCK_THREADS), lds_keys(8), s, w, lv);
+      } else {
+        allow_lds(k_scatter_keys<KT, 4>, lds_keys(4));
+        hipLaunchKernelGGL((k_scatter_keys<KT, 4>), dim3(grid_for(ls.tiles, 512)),
+                           dim3(SCK_THREADS), lds_keys(4), s, w, lv);
+      }
     }
   }
   if (!dbg_hist) {
