@@ -133,6 +133,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(SPECIAL))
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per load point")
+    ap.add_argument("--tune-trials", type=int, default=16,
+                    help="batch: parameter sets the autotuner may time")
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
     ap.add_argument("--cpu-sample-log2", type=int, default=27,
                     help="keys the parallel oracle sorts (log2)")
@@ -324,27 +326,41 @@ def bench_batch(args) -> int:
     lib = L.lib()
     s_ptr = stream.cuda_stream
 
-    # one batched call
-    wsb = api.batch_workspace_bytes(W.KEY_U64, offs)
-    ws = api.alloc_workspace(wsb, dev)
     d_offs = torch.from_numpy(offs.astype(np.int64)).to(dev)
-
-    def batched():
-        api.sort_batch(d_keys, offs, out_keys=d_out, d_offsets=d_offs, workspace=ws, stream=stream)
-
-    for _ in range(args.warmup):
-        batched()
-    torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def time_batched(params):
+        """ms per batched call (and host wall ms) with these parameters."""
+        wsb = api.batch_workspace_bytes(W.KEY_U64, offs, params=params)
+        ws = api.alloc_workspace(wsb, dev)
+
+        def batched():
+            api.sort_batch(d_keys, offs, out_keys=d_out, d_offsets=d_offs, params=params,
+                           workspace=ws, stream=stream)
+
+        for _ in range(args.warmup):
+            batched()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            batched()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        del ws
+        return ev0.elapsed_time(ev1) / args.steps, wall * 1e3
+
+    # the built-in defaults, then the autotuner's choice for this batch (the
+    # reported value); both sort into d_out and must agree
+    ms_d, _ = time_batched(None)
+    _log("batched, default parameters: %.3f ms per batch" % ms_d)
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        batched()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall_b = (time.perf_counter() - t0) / args.steps
-    ms_b = ev0.elapsed_time(ev1) / args.steps
-    _log("batched: %.3f ms per batch (wall %.3f ms)" % (ms_b, wall_b * 1e3))
+    tuned, tuned_ms = api.autotune(d_keys, offs, stream=stream, max_trials=args.tune_trials)
+    tune_s = time.perf_counter() - t0
+    _log("autotuned in %.1f s: %s (%.3f ms)" % (tune_s, api.params_dict(tuned), tuned_ms))
+    ms_b, wall_b = time_batched(tuned)
+    _log("batched, tuned parameters: %.3f ms per batch (wall %.3f ms)" % (ms_b, wall_b))
 
     # verify: every segment sorted on the device, sampled segments equal numpy's sort
     o = _flip64(d_out)
@@ -386,13 +402,18 @@ def bench_batch(args) -> int:
 
     value = total / (ms_b * 1e-3) / 1e9
     line = {
-        "metric": "batched sort throughput, GKeys/s (one persistent launch sequence vs one call per instance)",
+        "metric": "batched sort throughput, GKeys/s (one persistent launch sequence with autotuned "
+                  "parameters vs one call per instance)",
         "value": round(value, 3), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_b, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": args.workload, "segments": int(sizes.size), "keys": total,
                    "sizes": "floor(2^U), U ~ Uniform(8, 20)", "min_size": int(sizes.min()),
                    "max_size": int(sizes.max()), "median_size": int(np.median(sizes))},
+        "tuned_params": {k: v for k, v in api.params_dict(tuned).items() if v},
+        "autotune_s": round(tune_s, 2),
+        "default_params": {"value": round(total / (ms_d * 1e-3) / 1e9, 3), "unit": "GKeys/s",
+                           "ms": round(ms_d, 3)},
         "per_instance": {"value": round(total / (ms_p * 1e-3) / 1e9, 3), "unit": "GKeys/s",
                          "ms": round(ms_p, 3), "host_wall_ms": round(wall_p * 1e3, 3)},
         "speedup_vs_per_instance": round(ms_p / ms_b, 2),

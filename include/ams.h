@@ -115,6 +115,29 @@ ams_status ams_sort_batch(ams_key_t t, const void *d_kin, const uint32_t *d_vin,
                           size_t num, void *d_ws, size_t ws_bytes, void *stream,
                           const ams_params *p);
 
+/* Autotuner.  Times candidate parameter sets (levels, k, overpartition_b,
+ * base_cutoff, tile_keys; one changed at a time from the built-in defaults,
+ * keeping each improvement) for sorting the num segments h_offsets describes
+ * (num = 1, h_offsets = {0, n} for a single sort) of d_kin (and d_vin when
+ * non-NULL), and writes the fastest to *best (its time per sort in ms to
+ * *best_ms when non-NULL).  The input is only read: candidates sort into
+ * buffers the tuner allocates (about twice the input) and frees.  Every
+ * candidate's output must equal the first one's bit for bit, else AMS_EHIP.
+ * At most max_trials candidates are timed (0 = 24), each three times.
+ * Synchronises `stream`.  The choice is remembered for the process, keyed by
+ * the shape class (key type, payload, floor(log2) of the total, of the
+ * largest segment and of the segment count): later sort calls of that class
+ * whose ams_params leave a tuned field zero (or pass NULL) use it.  The
+ * workspace size of such a call follows the tuned parameters, so query
+ * ams_*workspace_bytes after tuning.  Section 7 chooses levels and group
+ * counts from the machine size; here they are measured. */
+ams_status ams_autotune(ams_key_t t, const void *d_kin, const uint32_t *d_vin,
+                        const uint64_t *h_offsets, size_t num, void *stream, uint32_t max_trials,
+                        ams_params *best, double *best_ms);
+
+/* Forget every autotuned choice of this process. */
+void ams_autotune_clear(void);
+
 /* Message for the calling thread's most recent error ("" if none). */
 const char *ams_last_error(void);
 

@@ -109,6 +109,8 @@ EXPORTS = [
     ("ams_step_level", _I, [_I, _P, _P, _SZ, _P, _U32, _U32, _U32, _P, _P, _P, _P]),
     ("ams_step_pack", _I, [_P, _U32, _U32, _P, _P]),
     ("ams_step_base_case", _I, [_I, _P, _P, _P, _P, _SZ, _U32, _P]),
+    ("ams_autotune", _I, [_I, _P, _P, _P, _SZ, _P, _U32, _P, _P]),
+    ("ams_autotune_clear", None, []),
 ]
 
 _lib = None

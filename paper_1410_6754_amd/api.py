@@ -135,6 +135,41 @@ def sort_batch(keys: torch.Tensor, offsets, vals: torch.Tensor | None = None,
     return (out_keys, out_vals) if vals is not None else out_keys
 
 
+def autotune(keys: torch.Tensor, offsets=None, vals: torch.Tensor | None = None, stream=None,
+             max_trials: int = 0):
+    """Time candidate parameter sets for sorting ``keys`` (segments given by
+    ``offsets``, one segment when None) and return (best Params, ms per sort).
+    The choice is also remembered for this shape class (see ams_autotune)."""
+    kt = key_type_of(keys)
+    _dev(keys, "keys")
+    if offsets is None:
+        offsets = [0, keys.numel()]
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    if offs.size < 2 or int(offs[-1]) != keys.numel():
+        raise ValueError("offsets must have num+1 entries ending at len(keys)")
+    vp = None
+    if vals is not None:
+        _dev(vals, "vals")
+        vp = vals.data_ptr()
+    best = Params()
+    ms = ctypes.c_double(0.0)
+    check(lib().ams_autotune(kt, keys.data_ptr(), vp, offs.ctypes.data, offs.size - 1,
+                             _stream(stream), max_trials, ctypes.byref(best), ctypes.byref(ms)))
+    return best, ms.value
+
+
+def autotune_clear():
+    """Forget every autotuned choice of this process."""
+    lib().ams_autotune_clear()
+
+
+def params_dict(p: Params | None) -> dict:
+    """The fields of an ams_params as a plain dict."""
+    if p is None:
+        return {}
+    return {name: getattr(p, name) for name, _ in Params._fields_}
+
+
 # ----------------------------------------------------------------------------
 # step entry points (one step of the path on one subproblem)
 # ----------------------------------------------------------------------------
@@ -194,7 +229,7 @@ __all__ = [
     "AMS_U32", "AMS_U64", "AMS_F32", "KT_TO_DTYPE", "key_type_of", "make_params",
     "workspace_bytes", "batch_workspace_bytes", "alloc_workspace", "sort_keys", "sort_pairs",
     "sort_batch", "step_splitters", "step_level", "step_pack", "step_base_case", "_lib",
-    "trace_start", "trace_stop",
+    "trace_start", "trace_stop", "autotune", "autotune_clear", "params_dict",
 ]
 
 

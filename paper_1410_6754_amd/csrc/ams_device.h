@@ -159,6 +159,39 @@ AMS_DEV uint64_t match_lanes(uint32_t c, bool valid, uint32_t nbits) {
   return m;
 }
 
+// Add 1 to counter ctr[c] for every active lane and return the lane's old
+// value (its slot).  When every active lane of the wavefront names the same
+// counter (sorted or heavily skewed input) one lane adds for all of them, so
+// the LDS atomics do not serialise on one address.  Call from uniform
+// control flow.
+AMS_DEV uint32_t wave_slot_add(uint32_t *ctr, uint32_t c, bool active) {
+  const uint64_t act = ballot(active);
+  if (act == 0) return 0;
+  const uint32_t lead = (uint32_t)__builtin_ctzll(act);
+  const uint32_t c0 = __builtin_amdgcn_readlane(c, lead);
+  if (ballot(active && c == c0) == act) {
+    uint32_t base = 0;
+    if (lane_id() == lead) base = atomicAdd(&ctr[c0], (uint32_t)__popcll(act));
+    base = __builtin_amdgcn_readlane(base, lead);
+    return base + bits_below(act);
+  }
+  return active ? atomicAdd(&ctr[c], 1u) : 0u;
+}
+
+// Add 1 to ctr[c] for every active lane (no slots returned), aggregated the
+// same way.
+AMS_DEV void wave_count_add(uint32_t *ctr, uint32_t c, bool active) {
+  const uint64_t act = ballot(active);
+  if (act == 0) return;
+  const uint32_t lead = (uint32_t)__builtin_ctzll(act);
+  const uint32_t c0 = __builtin_amdgcn_readlane(c, lead);
+  if (ballot(active && c == c0) == act) {
+    if (lane_id() == lead) atomicAdd(&ctr[c0], (uint32_t)__popcll(act));
+    return;
+  }
+  if (active) atomicAdd(&ctr[c], 1u);
+}
+
 template <typename T> AMS_DEV T wave_sum(T v) {
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
   return v;

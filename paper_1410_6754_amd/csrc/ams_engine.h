@@ -82,4 +82,8 @@ ams_status run_plan(const Plan &pl, void *ws, const RootSource &src, hipStream_t
 
 void set_error(const char *fmt, ...);
 
+// Parameters the autotuner chose for this shape class, if any (ams_tune.hip).
+bool tuned_lookup(int kt, bool pay, uint64_t total, uint64_t mx, uint64_t nroots,
+                  ams_params *out);
+
 }  // namespace ams

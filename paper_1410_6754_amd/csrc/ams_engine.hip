@@ -411,7 +411,7 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
 #pragma unroll
       for (uint32_t u = 0; u < CU; ++u) {
         const uint32_t p = base + (u / V) * (V * 256u) + V * tid + (u % V);
-        if (p < hi) atomicAdd(&sH[ids[u]], 1u);
+        wave_count_add(sH, ids[u], p < hi);
       }
     }
     __syncthreads();
@@ -592,6 +592,7 @@ struct PackSmem {
   uint32_t *aux;  // HS + 1 words of scan space
   uint16_t *pst;  // HS + 1 piece starts
   uint8_t *gs;    // HS + 8 flags: the greedy opens a group at this id
+  uint32_t *nzr;  // 2 (CH + 1) words: per child, first and end of its nonempty ids
 };
 
 AMS_HD size_t pack_al16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -612,11 +613,12 @@ AMS_HD size_t pack_layout(uint32_t HS, uint32_t CH, size_t *o) {
   o[10] = b; b = pack_al16(b + HS);                       // fin
   o[11] = b; b = pack_al16(b + CH);                       // kind
   o[12] = b; b = pack_al16(b + (size_t)HS + 8);           // gs
+  o[13] = b; b = pack_al16(b + 2 * ((size_t)CH + 1) * 4); // nzr
   return b;
 }
 
 AMS_DEV PackSmem pack_smem(unsigned char *base, uint32_t HS, uint32_t CH) {
-  size_t o[13];
+  size_t o[14];
   pack_layout(HS, CH, o);
   PackSmem p;
   p.tot = (uint32_t *)(base + o[0]);
@@ -632,6 +634,7 @@ AMS_DEV PackSmem pack_smem(unsigned char *base, uint32_t HS, uint32_t CH) {
   p.fin = base + o[10];
   p.kind = base + o[11];
   p.gs = base + o[12];
+  p.nzr = (uint32_t *)(base + o[13]);
   return p;
 }
 
@@ -755,19 +758,40 @@ __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
       p.first[nch] = (uint16_t)NB;
     }
     __syncthreads();
-    uint16_t *gF = w.cfirst + (size_t)i * (CH + 1);
+    uint16_t *gF = w.cfirst + (size_t)i * 2 * (CH + 1);
     uint32_t *gS = w.cstart + (size_t)i * (CH + 1);
     uint8_t *gD = w.cdst + (size_t)i * CH;
     uint16_t *gI = w.i2c + (size_t)i * HS;
     const bool inplace = root_inplace(R);
     const uint32_t srcbuf = seg_buf(s.meta), dst = seg_dst(s.meta);
     const bool finToOut = srcbuf == BUF_TMP || (srcbuf == BUF_IN && !inplace);
-    for (uint32_t c = tid; c <= nch; c += 256) {
-      gF[c] = p.first[c];
-      if (c < nch) gS[c] = p.start[c];
+    // id -> child map, and per child the range of ids that hold keys
+    // (gF[2c], gF[2c+1]): a child can span many empty ids (all-equal or
+    // heavily duplicated keys), which the tile scan then skips
+    uint32_t *nzr = p.nzr;
+    for (uint32_t c = tid; c < nch; c += 256) {
+      nzr[2 * c] = 0xFFFFu;
+      nzr[2 * c + 1] = 0;
+    }
+    __syncthreads();
+    for (uint32_t id = tid; id < NB; id += 256) {
+      uint32_t c = 0;  // the last child whose first id is <= id
+      for (uint32_t span = 1u << ilog2c(nch + 1); span; span >>= 1)
+        if (c + span < nch && p.first[c + span] <= id) c += span;
+      gI[id] = (uint16_t)c;
+      if (p.tot[id]) {
+        atomicMin(&nzr[2 * c], id);
+        atomicMax(&nzr[2 * c + 1], id + 1);
+      }
+    }
+    __syncthreads();
+    for (uint32_t c = tid; c < nch; c += 256) {
+      const uint32_t a = nzr[2 * c], b = nzr[2 * c + 1];
+      gF[2 * c] = (uint16_t)(a < b ? a : p.first[c]);
+      gF[2 * c + 1] = (uint16_t)(a < b ? b : p.first[c]);
+      gS[c] = p.start[c];
     }
     for (uint32_t c = tid; c < nch; c += 256) {
-      for (uint32_t id = p.first[c]; id < p.first[c + 1]; ++id) gI[id] = (uint16_t)c;
       const uint32_t off = s.off + p.start[c], size = p.sz[c];
       uint32_t cd;
       if (p.kind[c] == CHILD_REG) {
@@ -832,12 +856,12 @@ __global__ void __launch_bounds__(256) k_tile_scan(Ws w, Lev lv) {
     uint32_t t0 = w.tileStart[i] + bb * lv.TB;
     uint32_t t1 = t0 + lv.TB < w.tileStart[i + 1] ? t0 + lv.TB : w.tileStart[i + 1];
     uint32_t nch = w.nch[i];
-    const uint16_t *tf = w.cfirst + (size_t)i * (lv.CH + 1);
+    const uint16_t *tf = w.cfirst + (size_t)i * 2 * (lv.CH + 1);
     const uint32_t *cs = w.cstart + (size_t)i * (lv.CH + 1);
     const uint32_t *pre = w.blkHist + (size_t)B * lv.HS;  // prefix over earlier blocks
     const uint32_t c = ch * 256 + tid;
     if (c < nch) {
-      const uint32_t f = tf[c], e = tf[c + 1];
+      const uint32_t f = tf[2 * c], e = tf[2 * c + 1];  // the child's nonempty ids
       uint32_t run = cs[c];
       for (uint32_t id = f; id < e; ++id) run += pre[id];
       // the child's count in 8 tiles at a time (independent loads), then
@@ -1154,11 +1178,8 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
         const uint32_t p = cb + sck_pos<K, KPT>(k);
-        uint32_t c = 0, slot = 0;
-        if (p < hi) {
-          c = sI2C[xcs[k]];
-          slot = atomicAdd(&sCnt[c], 1u);
-        }
+        const uint32_t c = p < hi ? (uint32_t)sI2C[xcs[k]] : 0u;
+        const uint32_t slot = wave_slot_add(sCnt, c, p < hi);
         xcs[k] = (c << 16) | slot;
       }
       __syncthreads();
@@ -1958,6 +1979,23 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
   }
   pl.ntotal = total;
   pl.maxroot = mx;
+  // zero fields take the autotuner's choice for this shape class, if it has
+  // made one, and the built-in defaults otherwise
+  ams_params merged;
+  {
+    ams_params tuned;
+    if (tuned_lookup(kt, pay, total, mx, nroots, &tuned)) {
+      merged = p ? *p : tuned;
+      if (p) {
+        if (!merged.levels) merged.levels = tuned.levels;
+        if (!merged.k) merged.k = tuned.k;
+        if (!merged.overpartition_b) merged.overpartition_b = tuned.overpartition_b;
+        if (!merged.base_cutoff) merged.base_cutoff = tuned.base_cutoff;
+        if (!merged.tile_keys) merged.tile_keys = tuned.tile_keys;
+      }
+      p = &merged;
+    }
+  }
   uint32_t C = fin_capacity(pl.kw, pay);
   if (p && p->leaf_capacity) {
     // the base case needs room for its sample overlays (3 * FMAX keys); step
@@ -2082,7 +2120,7 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
   pl.o_totals = take(any ? (size_t)capAct * maxHS * 4 : 0);
   pl.o_tileOff = take(any ? (size_t)capTile * maxCH * 4 : 0);
   pl.o_i2c = take(any ? (size_t)capAct * maxHS * 2 : 0);
-  pl.o_cfirst = take(any ? (size_t)capAct * (maxCH + 1) * 2 : 0);
+  pl.o_cfirst = take(any ? (size_t)capAct * 2 * (maxCH + 1) * 2 : 0);
   pl.o_cstart = take(any ? (size_t)capAct * (maxCH + 1) * 4 : 0);
   pl.o_cdst = take(any ? (size_t)capAct * maxCH : 0);
   pl.o_nch = take(any ? (size_t)capAct * 4 : 0);
@@ -2225,7 +2263,7 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
       hipLaunchKernelGGL(k_block_scan, dim3(grid_for((uint64_t)ls.P * ((ls.HS + 255) / 256), 1024)),
                          dim3(256), 0, s, w, lv);
     }
-    size_t po[13];
+    size_t po[14];
     size_t ldsP = pack_layout(ls.HS, ls.CH, po);
     allow_lds(k_pack, ldsP);
     {

@@ -126,3 +126,44 @@ def test_stable_partition_flag_same_result(api, kt):
     out = to_host(api.sort_keys(to_dev(keys), params=p))
     want, _ = oracle.oracle_sort(kt, keys)
     assert np.array_equal(out.view(np.uint8), want.view(np.uint8))
+
+
+@pytest.mark.parametrize("pay", [False, True])
+def test_autotuned_parameters_sort_identically(api, pay):
+    # the autotuner's choice (and the remembered choice used by a call with
+    # default parameters) must give the oracle's output on every segment
+    rng = np.random.default_rng(35 + pay)
+    sizes = _segments(rng, 200, 8, 16)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    n = int(offs[-1])
+    keys = gen(U64, n, "uniform", 43 + pay)
+    vals = np.arange(n, dtype=np.uint32) if pay else None
+    dk = to_dev(keys)
+    dv = to_dev(vals) if pay else None
+    api.autotune_clear()
+    log("autotune pay=%s segments=%d total=%d" % (pay, sizes.size, n))
+    best, ms = api.autotune(dk, offs, vals=dv, max_trials=6)
+    log("tuned %s in %.3f ms" % (api.params_dict(best), ms))
+    assert ms > 0
+    assert best.k >= 2 and (best.k & (best.k - 1)) == 0
+    assert best.k * best.overpartition_b <= 2048
+    outs = [api.sort_batch(dk, offs, vals=dv, params=best), api.sort_batch(dk, offs, vals=dv)]
+    for out in outs:
+        ok = to_host(out[0] if pay else out)
+        ov = to_host(out[1]) if pay else None
+        for i in range(sizes.size):
+            a, b = int(offs[i]), int(offs[i + 1])
+            wk, wv = oracle.oracle_sort(U64, keys[a:b], None if vals is None else vals[a:b])
+            assert np.array_equal(ok[a:b], wk), i
+            if pay:
+                assert np.array_equal(ov[a:b], wv), i
+    api.autotune_clear()
+
+
+def test_autotune_rejects_bad_arguments(api):
+    from paper_1410_6754_amd._lib import AmsError
+    dk = to_dev(gen(U64, 1000, "uniform", 45))
+    with pytest.raises(ValueError):
+        api.autotune(dk, [0, 10])
+    with pytest.raises(AmsError):
+        api.autotune(dk, [5, 1000])  # offsets must start at 0
