@@ -408,10 +408,25 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
       }
       uint32_t ids[CU];
       classify_batch<K, CU>(xs, ids, sTree, sSpl, logm, eq);
+      // one add for the whole wavefront when all its keys share a bucket
+      // (sorted or skewed input), else one LDS atomic per key
+      const uint32_t ntv = base + 256u * CU <= hi ? 256u * CU : hi - base;  // valid keys
+      const uint64_t lanes = ballot(true);
+      const uint32_t c0 = __builtin_amdgcn_readlane(ids[0], (uint32_t)__builtin_ctzll(lanes));
+      bool same = true;
 #pragma unroll
       for (uint32_t u = 0; u < CU; ++u) {
         const uint32_t p = base + (u / V) * (V * 256u) + V * tid + (u % V);
-        wave_count_add(sH, ids[u], p < hi);
+        same = same && (p >= hi || ids[u] == c0);
+      }
+      if (ballot(same) == lanes && ntv == 256u * CU) {
+        if (tid % 64 == 0) atomicAdd(&sH[c0], 64u * CU);
+      } else {
+#pragma unroll
+        for (uint32_t u = 0; u < CU; ++u) {
+          const uint32_t p = base + (u / V) * (V * 256u) + V * tid + (u % V);
+          if (p < hi) atomicAdd(&sH[ids[u]], 1u);
+        }
       }
     }
     __syncthreads();
@@ -1380,6 +1395,22 @@ AMS_DEV uint32_t cross_block_rank(const K *blk, uint32_t b, K x, uint32_t part, 
 //     and the positions they leave empty are filled with the same bits.
 //     Keys after a bucket are larger (buckets follow key order) and the pad
 //     holds the largest value, so a scan may run past its bucket unmasked.
+// In-LDS fan-out of a leaf of s keys: the smallest power of two f <= FMAX
+// with s / f <= cutoff / 2 (1 when the leaf is not split).
+AMS_DEV uint32_t leaf_fanout(uint32_t s, uint32_t cutoff) {
+  uint32_t f = 1;
+  if (s > cutoff) {
+    const uint32_t tgt = cutoff / 2 > 4 ? cutoff / 2 : 4;
+    const uint32_t need = (s + tgt - 1) / tgt;
+    f = 2;
+    while (f < need && f < FMAX) f <<= 1;
+  }
+  return f;
+}
+// log2 of the oversampling factor a of a leaf's sample (a = 4, 2, 1; the
+// sample a * f holds at most FMAX keys)
+AMS_DEV uint32_t leaf_loga(uint32_t logf) { return logf <= 6 ? 2u : 8u - logf; }
+
 template <int KT, bool PAY>
 AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
                       const typename Key<KT>::T *src, const uint32_t *vsrc, bool enc_in,
@@ -1387,13 +1418,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
                       uint32_t C, uint32_t cutoff, uint64_t st) {
   typedef typename Key<KT>::T K;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  uint32_t f = 1;
-  if (s > cutoff) {
-    uint32_t tgt = cutoff / 2 > 4 ? cutoff / 2 : 4;
-    uint32_t need = (s + tgt - 1) / tgt;
-    f = 2;
-    while (f < need && f < FMAX) f <<= 1;
-  }
+  const uint32_t f = leaf_fanout(s, cutoff);
   const uint32_t logf = ilog2c(f);
   // placed-position bitmap: position p is bit p / nwb of word p % nwb, so
   // neighbouring positions fall in different words (C <= 32 * nwb)
@@ -1402,6 +1427,13 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   static_assert(2 * FMAX == FIN_THREADS, "one bucket counter per thread");
   if (!PAY) sm.cnt[tid] = 0;  // keys-only bucket counters (the previous call ended on a barrier)
   const K *spl = sm.srt + 1;  // spl[b] = splitter just above bucket b
+  // The sample (S = a*f keys at random positions, drawn from the leaf's
+  // SplitMix64 stream) is requested before the leaf itself: ranking it then
+  // overlaps the arrival of the leaf's keys.
+  const uint32_t loga = leaf_loga(logf);               // a = 4, 2, 1
+  const uint32_t logS = logf + loga;                   // S <= FMAX = 256
+  const uint32_t S = f > 1 ? 1u << logS : 0u;
+  const K ysmp = tid < S ? src[draw_pos(st, tid, s)] : (K)0;
   K xk[FIN_KPT];
   uint32_t xv[FIN_KPT];
   uint32_t xir[FIN_KPT];  // id << 16 | slot
@@ -1422,14 +1454,9 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     // sample's elements of rank a*j - 1, j = 1..f-1.  At most FMAX samples:
     // ranking a larger sample costs more than the better balanced buckets
     // save in the all-pairs step.  Sizes are powers of two (shifts only).
-    const uint32_t loga = logf <= 6 ? 2u : 8u - logf;   // a = 4, 2, 1
-    const uint32_t logS = logf + loga;                   // S <= FMAX = 256
     const uint32_t logH = 9u - logS < 3u ? 9u - logS : 3u;  // H = min(512 / S, 8)
-    const uint32_t S = 1u << logS, H = 1u << logH, amask = (1u << loga) - 1u;
-    if (tid < S) {
-      const K y = src[draw_pos(st, tid, s)];
-      sm.smp[tid] = enc_in ? Key<KT>::enc(y) : y;
-    }
+    const uint32_t H = 1u << logH, amask = (1u << loga) - 1u;
+    if (tid < S) sm.smp[tid] = enc_in ? Key<KT>::enc(ysmp) : ysmp;
     __syncthreads();
     // Rank the sample (Section 4.2): inside blocks of up to 64 by comparing
     // all pairs, then across blocks by binary search.  H adjacent lanes share
@@ -1505,6 +1532,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       xir[k] = (xir[k] << 16) | slot;
     }
     __syncthreads();
+    if (tid < 65) ((uint32_t *)sm.srt)[tid] = 0;  // work-order counters (splitters are done)
     // exclusive scan of the NB <= FIN_THREADS bucket sizes (one per thread)
     // and the largest bucket, from per-wave totals and maxima
     const uint32_t cv = tid < NB ? sm.cnt[tid] : 0u;
@@ -1541,6 +1569,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     const uint32_t nbits = ilog2c(NB);
     for (uint32_t q = tid; q < 8 * NB; q += FIN_THREADS) sm.cnt[q] = 0;
     __syncthreads();
+    if (tid < 65) ((uint32_t *)sm.srt)[tid] = 0;  // work-order counters (splitters are done)
 #pragma unroll
     for (uint32_t k = 0; k < FIN_KPT; ++k) {
       const uint32_t p = (wave * spw + k) * 64 + lane;
@@ -1601,41 +1630,33 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   const bool padded = s + Lb + 8 <= C + FIN_PAD;
   // ---- work order.  A wavefront ranks its keys in a common trip count,
   // the longest bucket among its lanes, so the keys are handed to lanes
-  // bucket by bucket in order of decreasing bucket size (64 size classes,
-  // counting sort): a wavefront then holds buckets of about one size.
-  // Equality buckets come last; their keys are not ranked.  Lane slot p
-  // belongs to bucket id map(p) and holds the key at B position
+  // bucket by bucket in order of decreasing bucket size (64 size classes):
+  // a wavefront then holds buckets of about one size.  Equality buckets
+  // come last (class 64); their keys are not ranked.  Buckets of a class
+  // follow one another in the order their atomic adds happened.  Lane slot
+  // p belongs to bucket id map(p) and holds the key at B position
   // bstart[id] + p - lofs[id].
   uint16_t *lofs = PAY ? (uint16_t *)sm.cnt : (uint16_t *)(sm.cnt + nwb);  // NB first slots
-  uint32_t *hist = (uint32_t *)sm.srt;  // 64 class counters, then the start of equality slots
+  uint32_t *hist = (uint32_t *)sm.srt;  // keys per class (cleared in the split); [64]: start of equality slots
   {
-    if (tid < 64) hist[tid] = 0;
-    __syncthreads();
     const bool haveId = tid < NB;
     const bool eqId = eq && (tid & 1u);
-    uint32_t L = 0, cls = 0, slot = 0;
+    uint32_t L = 0, cls = 0, kslot = 0;
     if (haveId) {
       L = sm.bstart[tid + 1] - sm.bstart[tid];
-      cls = 63u - (L < 63u ? L : 63u);
-      if (!eqId) slot = atomicAdd(&hist[cls], 1u);
+      cls = eqId ? 64u : 63u - (L < 63u ? L : 63u);
+      kslot = atomicAdd(&hist[cls], L);
     }
     __syncthreads();
-    if (wave == 0) {
+    if (wave == 0) {  // class starts: exclusive scan of classes 0..63, class 64 after them
       const uint32_t c = hist[lane];
-      hist[lane] = wave_incl_scan(c) - c;
+      const uint32_t inc = wave_incl_scan(c);
+      hist[lane] = inc - c;
+      if (lane == 63) hist[64] = inc;
     }
     __syncthreads();
-    // order: regular ids by class, then the equality ids (odd ids) in order
-    const uint32_t ord = eqId ? f + (tid >> 1) : hist[cls] + slot;
-    uint32_t *sc = sm.cnt;  // NB words: key counts in work order, then their scan
-    if (haveId) sc[ord] = L;
-    __syncthreads();
-    block_exscan<FIN_THREADS>(sc, NB, sm.wred);
-    const uint32_t lo = haveId ? sc[ord] : 0u;
-    const uint32_t eqStart = eq ? sc[f] : s;
-    __syncthreads();
-    if (tid == 0) hist[64] = eqStart;
     if (haveId) {
+      const uint32_t lo = hist[cls] + kslot;
       lofs[tid] = (uint16_t)lo;
       const uint32_t bb = eq ? tid >> 1 : tid, word = bb * 0x01010101u;
       uint32_t j = lo;
