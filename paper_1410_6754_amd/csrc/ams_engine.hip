@@ -1427,36 +1427,165 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   static_assert(2 * FMAX == FIN_THREADS, "one bucket counter per thread");
   if (!PAY) sm.cnt[tid] = 0;  // keys-only bucket counters (the previous call ended on a barrier)
   const K *spl = sm.srt + 1;  // spl[b] = splitter just above bucket b
-  // The sample (S = a*f keys at random positions, drawn from the leaf's
-  // SplitMix64 stream) is requested before the leaf itself: ranking it then
-  // overlaps the arrival of the leaf's keys.
-  const uint32_t loga = leaf_loga(logf);               // a = 4, 2, 1
-  const uint32_t logS = logf + loga;                   // S <= FMAX = 256
-  const uint32_t S = f > 1 ? 1u << logS : 0u;
-  const K ysmp = tid < S ? src[draw_pos(st, tid, s)] : (K)0;
   K xk[FIN_KPT];
   uint32_t xv[FIN_KPT];
   uint32_t xir[FIN_KPT];  // id << 16 | slot
   // keys into registers; pairs: waves own contiguous ranges (stable split)
   const uint32_t nsteps = (s + 63) / 64, spw = (nsteps + 7) / 8;
+  auto slot_pos = [&](uint32_t k) -> uint32_t {
+    return PAY ? (wave * spw + k) * 64 + lane : tid + FIN_THREADS * k;
+  };
+  auto slot_valid = [&](uint32_t k) -> bool {
+    return PAY ? (k < spw && slot_pos(k) < s) : slot_pos(k) < s;
+  };
 #pragma unroll
   for (uint32_t k = 0; k < FIN_KPT; ++k) {
-    const uint32_t p = PAY ? (wave * spw + k) * 64 + lane : tid + FIN_THREADS * k;
-    const bool valid = PAY ? (k < spw && p < s) : p < s;
+    const uint32_t p = slot_pos(k);
+    const bool valid = slot_valid(k);
     K x = valid ? src[p] : (K)0;
     xk[k] = enc_in ? Key<KT>::enc(x) : x;
     if (PAY) xv[k] = valid ? vsrc[p] : 0u;
   }
+
+  // Bucket counts, their exclusive scan (bstart) and the largest bucket for
+  // ids xir[k] of the valid slots.  Keys only: slot = LDS atomic (the
+  // counters are zero on entry); pairs: rank among equal ids of the wave's
+  // range by ballots, then per-wave rows, so input order is kept.  Returns
+  // the largest bucket; ends with a barrier.
+  auto count_scan = [&](uint32_t NB) -> uint32_t {
+    uint32_t Lmax = 0;
+    if (!PAY) {
+#pragma unroll
+      for (uint32_t k = 0; k < FIN_KPT; ++k) {
+        uint32_t slot = 0;
+        if (slot_valid(k)) slot = atomicAdd(&sm.cnt[xir[k]], 1u);
+        xir[k] = (xir[k] << 16) | slot;
+      }
+      __syncthreads();
+      const uint32_t cv = tid < NB ? sm.cnt[tid] : 0u;
+      const uint32_t inc = wave_incl_scan(cv);
+      const uint32_t wmx = wave_max(cv);
+      if (lane == 63) {
+        sm.wred[wave] = inc;
+        sm.wred[8 + wave] = wmx;
+      }
+      __syncthreads();
+      uint32_t off = 0;
+#pragma unroll
+      for (uint32_t ww = 0; ww < FIN_THREADS / 64; ++ww) {
+        off += ww < wave ? sm.wred[ww] : 0u;
+        Lmax = sm.wred[8 + ww] > Lmax ? sm.wred[8 + ww] : Lmax;
+      }
+      if (tid < NB) sm.bstart[tid] = off + inc - cv;
+      if (tid == 0) sm.bstart[NB] = s;
+      __syncthreads();
+    } else {
+      const uint32_t nbits = ilog2c(NB);
+      for (uint32_t q = tid; q < 8 * NB; q += FIN_THREADS) sm.cnt[q] = 0;
+      __syncthreads();
+#pragma unroll
+      for (uint32_t k = 0; k < FIN_KPT; ++k) {
+        const bool valid = slot_valid(k);
+        const uint32_t id = valid ? xir[k] : 0u;
+        uint64_t peers = match_lanes(id, valid, nbits);
+        uint32_t below = bits_below(peers);
+        uint32_t r = 0;
+        if (valid) {
+          uint32_t *c = sm.cnt + wave * NB + id;
+          r = *c + below;
+          if (below == 0) *c = r + (uint32_t)__popcll(peers);
+        }
+        xir[k] = (id << 16) | r;
+      }
+      __syncthreads();
+      for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
+        uint32_t sum = 0;
+        for (uint32_t ww = 0; ww < 8; ++ww) sum += sm.cnt[ww * NB + id];
+        sm.bstart[id] = sum;
+      }
+      __syncthreads();
+      block_exscan<FIN_THREADS>(sm.bstart, NB, sm.tmp);
+      uint32_t *shMax = sm.wred;
+      if (tid == 0) {
+        sm.bstart[NB] = s;
+        *shMax = 0;
+      }
+      for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
+        uint32_t run = sm.bstart[id];
+        for (uint32_t ww = 0; ww < 8; ++ww) {
+          uint32_t v = sm.cnt[ww * NB + id];
+          sm.cnt[ww * NB + id] = run;
+          run += v;
+        }
+      }
+      __syncthreads();
+      if (tid < NB) atomicMax(shMax, sm.bstart[tid + 1] - sm.bstart[tid]);
+      __syncthreads();
+      Lmax = *shMax;
+    }
+    return Lmax;
+  };
+
   bool eq = false;
+  uint32_t NB = 1, Lb = 0;
+  bool split = false;  // xir / bstart hold an accepted split
   if (f > 1) {
-    // S = a*f sampled keys, read straight from the source (the leaf's lines
-    // are being fetched by the loads above); the splitters are the sorted
-    // sample's elements of rank a*j - 1, j = 1..f-1.  At most FMAX samples:
-    // ranking a larger sample costs more than the better balanced buckets
-    // save in the all-pairs step.  Sizes are powers of two (shifts only).
+    // ---- split by key range.  After the partition levels a leaf covers a
+    // narrow range of keys, which most inputs fill about evenly; bucket b(x)
+    // = (x - min) >> sh with sh chosen so that b < f.  b is monotone in x, so
+    // buckets follow key order and equal keys share a bucket.  The split is
+    // kept when no bucket exceeds 4x the average (at least 64 keys); else
+    // the sampled split below is used.
+    K mn = (K)~(K)0, mx = (K)0;
+#pragma unroll
+    for (uint32_t k = 0; k < FIN_KPT; ++k) {
+      if (slot_valid(k)) {
+        mn = xk[k] < mn ? xk[k] : mn;
+        mx = xk[k] > mx ? xk[k] : mx;
+      }
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    K *red = sm.srt;  // per-wave minima and maxima (the splitters are not drawn yet)
+    if (lane == 0) {
+      red[wave] = mn;
+      red[8 + wave] = mx;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t ww = 0; ww < FIN_THREADS / 64; ++ww) {
+      mn = red[ww] < mn ? red[ww] : mn;
+      mx = red[8 + ww] > mx ? red[8 + ww] : mx;
+    }
+    const K range = mx - mn;
+    const uint32_t bits = range ? (uint32_t)(8 * sizeof(K)) - (uint32_t)(sizeof(K) == 8
+                                       ? __builtin_clzll((unsigned long long)range)
+                                       : __builtin_clz((uint32_t)range))
+                                : 0u;
+    const uint32_t sh = bits > logf ? bits - logf : 0u;
+#pragma unroll
+    for (uint32_t k = 0; k < FIN_KPT; ++k)
+      xir[k] = slot_valid(k) ? (uint32_t)((xk[k] - mn) >> sh) : 0u;
+    NB = f;
+    Lb = count_scan(NB);
+    const uint32_t avg = (s + f - 1) / f;
+    split = Lb <= (4 * avg > 64 ? 4 * avg : 64);
+    if (!split && !PAY) sm.cnt[tid] = 0;  // counters for the sampled split
+  }
+  if (f > 1 && !split) {
+    // ---- sampled split: S = a*f keys at random positions of the leaf
+    // (SplitMix64 stream); the splitters are the sorted sample's elements of
+    // rank a*j - 1, j = 1..f-1.  At most FMAX samples: ranking a larger
+    // sample costs more than the better balanced buckets save in the
+    // all-pairs step.  Sizes are powers of two (shifts only).
+    const uint32_t loga = leaf_loga(logf);               // a = 4, 2, 1
+    const uint32_t logS = logf + loga;                   // S <= FMAX = 256
     const uint32_t logH = 9u - logS < 3u ? 9u - logS : 3u;  // H = min(512 / S, 8)
-    const uint32_t H = 1u << logH, amask = (1u << loga) - 1u;
-    if (tid < S) sm.smp[tid] = enc_in ? Key<KT>::enc(ysmp) : ysmp;
+    const uint32_t S = 1u << logS, H = 1u << logH, amask = (1u << loga) - 1u;
+    if (tid < S) {
+      const K y = src[draw_pos(st, tid, s)];
+      sm.smp[tid] = enc_in ? Key<KT>::enc(y) : y;
+    }
     __syncthreads();
     // Rank the sample (Section 4.2): inside blocks of up to 64 by comparing
     // all pairs, then across blocks by binary search.  H adjacent lanes share
@@ -1515,116 +1644,28 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     }
     eq = __syncthreads_or(dup ? 1 : 0) != 0;
     classify_halves<K>(xk, xir, sm.tree, spl, logf, eq, s);
-  } else {
+    NB = eq ? 2 * f - 1 : f;
+    Lb = count_scan(NB);
+  } else if (f == 1) {
 #pragma unroll
     for (uint32_t k = 0; k < FIN_KPT; ++k) xir[k] = 0;
+    __syncthreads();  // keys-only counters were cleared on entry
+    NB = 1;
+    Lb = count_scan(NB);
   }
-  const uint32_t NB = f == 1 ? 1 : (eq ? 2 * f - 1 : f);
-  uint32_t Lb;  // largest bucket
-  if (!PAY) {
-    // ---- keys only: unstable split with LDS atomics ----
-    if (f == 1) __syncthreads();  // counters were cleared on entry
+  if (tid < 65) ((uint32_t *)sm.srt)[tid] = 0;  // work-order counters (splitters are done)
+  // ---- place every key at its bucket's range in B
 #pragma unroll
-    for (uint32_t k = 0; k < FIN_KPT; ++k) {
-      const uint32_t p = tid + FIN_THREADS * k;
-      uint32_t slot = 0;
-      if (p < s) slot = atomicAdd(&sm.cnt[xir[k]], 1u);
-      xir[k] = (xir[k] << 16) | slot;
+  for (uint32_t k = 0; k < FIN_KPT; ++k) {
+    if (slot_valid(k)) {
+      const uint32_t id = xir[k] >> 16;
+      const uint32_t q = (PAY ? sm.cnt[wave * NB + id] : sm.bstart[id]) + (xir[k] & 0xFFFFu);
+      sm.B[q] = xk[k];
+      if (PAY) sm.vB[q] = xv[k];
     }
-    __syncthreads();
-    if (tid < 65) ((uint32_t *)sm.srt)[tid] = 0;  // work-order counters (splitters are done)
-    // exclusive scan of the NB <= FIN_THREADS bucket sizes (one per thread)
-    // and the largest bucket, from per-wave totals and maxima
-    const uint32_t cv = tid < NB ? sm.cnt[tid] : 0u;
-    const uint32_t inc = wave_incl_scan(cv);
-    const uint32_t wmx = wave_max(cv);
-    if (lane == 63) {
-      sm.wred[wave] = inc;
-      sm.wred[8 + wave] = wmx;
-    }
-    __syncthreads();
-    uint32_t off = 0;
-    Lb = 0;
-#pragma unroll
-    for (uint32_t ww = 0; ww < FIN_THREADS / 64; ++ww) {
-      off += ww < wave ? sm.wred[ww] : 0u;
-      Lb = sm.wred[8 + ww] > Lb ? sm.wred[8 + ww] : Lb;
-    }
-    if (tid < NB) sm.bstart[tid] = off + inc - cv;
-    if (tid == 0) sm.bstart[NB] = s;
-    __syncthreads();
-#pragma unroll
-    for (uint32_t k = 0; k < FIN_KPT; ++k) {
-      const uint32_t p = tid + FIN_THREADS * k;
-      if (p < s) {
-        const uint32_t id = xir[k] >> 16;
-        const uint32_t q = sm.bstart[id] + (xir[k] & 0xFFFFu);
-        sm.B[q] = xk[k];
-      }
-    }
-    if (s + Lb + 8 <= C + FIN_PAD)
-      for (uint32_t q = s + tid; q < s + Lb + 8; q += FIN_THREADS) sm.B[q] = (K)~(K)0;
-  } else {
-    // ---- pairs: stable split, ballot ranks inside each wave's range ----
-    const uint32_t nbits = ilog2c(NB);
-    for (uint32_t q = tid; q < 8 * NB; q += FIN_THREADS) sm.cnt[q] = 0;
-    __syncthreads();
-    if (tid < 65) ((uint32_t *)sm.srt)[tid] = 0;  // work-order counters (splitters are done)
-#pragma unroll
-    for (uint32_t k = 0; k < FIN_KPT; ++k) {
-      const uint32_t p = (wave * spw + k) * 64 + lane;
-      const bool valid = k < spw && p < s;
-      const uint32_t id = valid ? xir[k] : 0u;
-      uint64_t peers = match_lanes(id, valid, nbits);
-      uint32_t below = bits_below(peers);
-      uint32_t r = 0;
-      if (valid) {
-        uint32_t *c = sm.cnt + wave * NB + id;
-        r = *c + below;
-        if (below == 0) *c = r + (uint32_t)__popcll(peers);
-      }
-      xir[k] = (id << 16) | r;
-    }
-    __syncthreads();
-    for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
-      uint32_t sum = 0;
-      for (uint32_t ww = 0; ww < 8; ++ww) sum += sm.cnt[ww * NB + id];
-      sm.bstart[id] = sum;
-    }
-    __syncthreads();
-    block_exscan<FIN_THREADS>(sm.bstart, NB, sm.tmp);
-    for (uint32_t id = tid; id < NB; id += FIN_THREADS) {
-      uint32_t run = sm.bstart[id];
-      for (uint32_t ww = 0; ww < 8; ++ww) {
-        uint32_t v = sm.cnt[ww * NB + id];
-        sm.cnt[ww * NB + id] = run;
-        run += v;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (uint32_t k = 0; k < FIN_KPT; ++k) {
-      const uint32_t p = (wave * spw + k) * 64 + lane;
-      if (k < spw && p < s) {
-        const uint32_t id = xir[k] >> 16;
-        const uint32_t q = sm.cnt[wave * NB + id] + (xir[k] & 0xFFFFu);
-        sm.B[q] = xk[k];
-        sm.vB[q] = xv[k];
-      }
-    }
-    // largest bucket, for the sentinel pad
-    uint32_t *shMax = sm.wred;
-    if (tid == 0) {
-      sm.bstart[NB] = s;
-      *shMax = 0;
-    }
-    __syncthreads();
-    if (tid < NB) atomicMax(shMax, sm.bstart[tid + 1] - sm.bstart[tid]);
-    __syncthreads();
-    Lb = *shMax;
-    if (s + Lb + 8 <= C + FIN_PAD)
-      for (uint32_t q = s + tid; q < s + Lb + 8; q += FIN_THREADS) sm.B[q] = (K)~(K)0;
   }
+  if (s + Lb + 8 <= C + FIN_PAD)
+    for (uint32_t q = s + tid; q < s + Lb + 8; q += FIN_THREADS) sm.B[q] = (K)~(K)0;
   __syncthreads();
   // scans of at most Lb + 7 slots past a bucket start stay inside B
   const bool padded = s + Lb + 8 <= C + FIN_PAD;
