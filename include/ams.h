@@ -79,6 +79,9 @@ typedef struct {
 #define AMS_FLAG_STABLE_PARTITION 2u /* keys-only: partition levels keep input order inside
                                         every child (pairs always do); the sorted output is
                                         the same either way */
+#define AMS_FLAG_SAMPLED_LEAF_SPLIT 4u /* base case: split every leaf by sampled splitters
+                                          instead of first trying its key range; the sorted
+                                          output is the same either way (test hook) */
 
 /* Bytes of device workspace a call with these arguments needs.  Returns 0 on
  * invalid arguments.  ams_sort_* accept d_ws = NULL, in which case they

@@ -27,6 +27,7 @@ AMS_ENOTFOUND = -6
 
 AMS_FLAG_EQ_ALWAYS = 1
 AMS_FLAG_STABLE_PARTITION = 2
+AMS_FLAG_SAMPLED_LEAF_SPLIT = 4
 
 _STATUS = {0: "AMS_OK", -1: "AMS_EINVAL", -2: "AMS_ENOMEM", -3: "AMS_EHIP",
            -4: "AMS_EAGAIN", -5: "AMS_EUNSUPPORTED", -6: "AMS_ENOTFOUND"}

@@ -1415,7 +1415,7 @@ template <int KT, bool PAY>
 AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
                       const typename Key<KT>::T *src, const uint32_t *vsrc, bool enc_in,
                       typename Key<KT>::T *dst, uint32_t *vdst, bool dec_out, uint32_t s,
-                      uint32_t C, uint32_t cutoff, uint64_t st) {
+                      uint32_t C, uint32_t cutoff, uint64_t st, bool sampled_only) {
   typedef typename Key<KT>::T K;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t f = leaf_fanout(s, cutoff);
@@ -1529,7 +1529,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   bool eq = false;
   uint32_t NB = 1, Lb = 0;
   bool split = false;  // xir / bstart hold an accepted split
-  if (f > 1) {
+  if (f > 1 && !sampled_only) {
     // ---- split by key range.  After the partition levels a leaf covers a
     // narrow range of keys, which most inputs fill about evenly; bucket b(x)
     // = (x - min) >> sh with sh chosen so that b < f.  b is monotone in x, so
@@ -1860,7 +1860,8 @@ AMS_DEV void wg_merge(const typename Key<KT>::T *A, const uint32_t *vA, uint32_t
 
 template <int KT, bool PAY>
 __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint32_t C, uint32_t cutoff,
-                                                        uint64_t seed) {
+                                                        uint64_t seed, uint32_t flags) {
+  const bool sampled_only = (flags & AMS_FLAG_SAMPLED_LEAF_SPLIT) != 0;
   typedef typename Key<KT>::T K;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   FinSmem<K> sm = fin_smem<K, PAY>(smem_raw, C);
@@ -1888,7 +1889,8 @@ __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint3
     }
     const uint64_t st = stream_state(seed, LEAF_STREAM, L.root, L.off);
     if (kind == LEAF_REG) {
-      lds_sort<KT, PAY>(sm, src, vsrc, buf == BUF_IN, dst, vdst, true, L.size, C, cutoff, st);
+      lds_sort<KT, PAY>(sm, src, vsrc, buf == BUF_IN, dst, vdst, true, L.size, C, cutoff, st,
+                        sampled_only);
       continue;
     }
     // Oversized leaf (a group larger than LDS after the planned levels):
@@ -1906,7 +1908,7 @@ __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint3
       uint32_t o = r * C, sz = n - o < C ? n - o : C;
       lds_sort<KT, PAY>(sm, src + o, PAY ? vsrc + o : nullptr, buf == BUF_IN, bufK[curb] + o,
                         PAY ? bufV[curb] + o : nullptr, false, sz, C, cutoff,
-                        stream_state(seed, LEAF_STREAM, L.root, L.off + o));
+                        stream_state(seed, LEAF_STREAM, L.root, L.off + o), sampled_only);
     }
     for (uint32_t pz = 0; pz < passes; ++pz) {
       const uint32_t width = C << pz;
@@ -2381,7 +2383,7 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
     allow_lds(k_finish<KT, PAY>, ldsF);
     TraceScope ts("finish", 0xFFFFFFFFu, s);
     hipLaunchKernelGGL((k_finish<KT, PAY>), dim3(grid_for(pl.capLeaf, PAY ? 256 : 512)),
-                       dim3(FIN_THREADS), ldsF, s, w, pl.C, pl.cutoff, pl.seed);
+                       dim3(FIN_THREADS), ldsF, s, w, pl.C, pl.cutoff, pl.seed, pl.flags);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {

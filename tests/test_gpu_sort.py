@@ -93,3 +93,13 @@ def test_determinism(api):
     a = to_host(api.sort_keys(d))
     b = to_host(api.sort_keys(d))
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_sampled_leaf_split_full_sort(api, dist):
+    # two partition levels with every leaf split by sampled splitters
+    n = 1_500_000
+    keys = gen(U64, n, dist, 91)
+    p = api.make_params(levels=2, k=64, overpartition_b=4, flags=4)  # AMS_FLAG_SAMPLED_LEAF_SPLIT
+    log("sampled leaf split %s n=%d" % (dist, n))
+    check_sort_keys(api, U64, keys, params=p, what="sampled leaf split")

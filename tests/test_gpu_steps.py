@@ -130,6 +130,28 @@ def test_base_case_cutoffs(api, kt, cutoff, dist):
     assert np.array_equal(to_host(ov), wv)
 
 
+@pytest.mark.parametrize("kt", [U64, U32, F32])
+@pytest.mark.parametrize("dist", ["uniform", "sorted", "zipf", "few", "specials"])
+@pytest.mark.parametrize("split", ["range", "sampled"])
+def test_base_case_split_kinds(api, kt, dist, split):
+    # the key-range split (kept when balanced) and the sampled split give the
+    # same output; the flag forces the sampled one on every leaf (float32
+    # "uniform" keys are normal(0, 1))
+    n = 7777
+    keys = gen(kt, n, dist, 77)
+    flags = 4 if split == "sampled" else 0  # AMS_FLAG_SAMPLED_LEAF_SPLIT
+    p = api.make_params(base_cutoff=32, flags=flags)
+    log("split kinds kt=%d %s %s" % (kt, dist, split))
+    out = to_host(api.sort_keys(to_dev(keys), params=p))
+    want, _ = oracle.oracle_sort(kt, keys)
+    assert np.array_equal(out.view(np.uint8), want.view(np.uint8))
+    vals = np.arange(n, dtype=np.uint32)
+    ok, ov = api.sort_pairs(to_dev(keys), to_dev(vals), params=p)
+    wk, wv = oracle.oracle_sort(kt, keys, vals)
+    assert np.array_equal(to_host(ok).view(np.uint8), wk.view(np.uint8))
+    assert np.array_equal(to_host(ov), wv)
+
+
 def test_all_pairs_rank_definition_on_gpu(api):
     # base case with one bucket (n <= cutoff): the result is the all-pairs
     # rank placement of Section 4.2
