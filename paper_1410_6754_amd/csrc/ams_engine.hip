@@ -1175,11 +1175,11 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
       for (uint32_t c = tid; c < nch; c += SCK_THREADS) sCd[c] = gd[c];
       gSpl = (const K *)w.spl + (size_t)i * lv.mmax;
       cur = i;
+      __syncthreads();  // the subproblem's tables are in LDS
     }
     // sBase[c]: this tile's next output offset of child c (read and
-    // advanced only by thread c % SCK_THREADS)
+    // advanced only by thread c % SCK_THREADS, so no barrier is needed)
     for (uint32_t c = tid; c < nch; c += SCK_THREADS) sBase[c] = w.tileOff[(size_t)g * CH + c];
-    __syncthreads();
     for (uint32_t cb = lo; cb < hi; cb += CHK) {
       K xb[KPT];
       if (cb + CHK < hi) sck_load<KT, KPT>(rs, (cb + CHK - lo) * (uint32_t)sizeof(K), xb);
@@ -1213,6 +1213,7 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
         }
         sDst[c] = d;
         sBase[c] += sCnt[c];
+        sCnt[c] = 0;  // its last use in this chunk: ready for the next one
       }
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
@@ -1244,8 +1245,9 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
           *(K *)((d & ~(uint64_t)1) + (uint64_t)q * sizeof(K)) = x;
         }
       }
-      for (uint32_t c = tid; c < nch; c += SCK_THREADS) sCnt[c] = 0;
-      __syncthreads();
+      // no barrier here: every wavefront finishes this write-out before it
+      // reaches the next chunk's first barrier, and the staging area is
+      // only written after that barrier
 #pragma unroll
       for (int k = 0; k < KPT; ++k) xa[k] = xb[k];
     }
@@ -1529,6 +1531,16 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   bool eq = false;
   uint32_t NB = 1, Lb = 0;
   bool split = false;  // xir / bstart hold an accepted split
+  // uint64 keys only: B holds z = (x - zmn) << zlsh, the offset from the
+  // leaf's minimum shifted to the top of the word.  z is monotone in x and
+  // its high 32 bits order any two keys whose offsets differ in their
+  // leading 32 significant bits, so the ranking compares 32-bit words; keys
+  // that tie there share a rank and are put right by the exact pass at the
+  // end, like equal keys.
+  constexpr bool ZT = KT == KT_U64 && !PAY;
+  bool zt = false;
+  K zmn = 0;
+  uint32_t zlsh = 0;
   if (f > 1 && !sampled_only) {
     // ---- split by key range.  After the partition levels a leaf covers a
     // narrow range of keys, which most inputs fill about evenly; bucket b(x)
@@ -1566,6 +1578,11 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
 #pragma unroll
     for (uint32_t k = 0; k < FIN_KPT; ++k)
       xir[k] = slot_valid(k) ? (uint32_t)((xk[k] - mn) >> sh) : 0u;
+    if (ZT && bits > 0) {
+      zt = true;
+      zmn = mn;
+      zlsh = (uint32_t)(8 * sizeof(K)) - bits;
+    }
     NB = f;
     Lb = count_scan(NB);
     const uint32_t avg = (s + f - 1) / f;
@@ -1660,7 +1677,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     if (slot_valid(k)) {
       const uint32_t id = xir[k] >> 16;
       const uint32_t q = (PAY ? sm.cnt[wave * NB + id] : sm.bstart[id]) + (xir[k] & 0xFFFFu);
-      sm.B[q] = xk[k];
+      sm.B[q] = (ZT && zt) ? (K)((xk[k] - zmn) << zlsh) : xk[k];
       if (PAY) sm.vB[q] = xv[k];
     }
   }
@@ -1737,7 +1754,18 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       // one counter per unrolled element: each compare then feeds a single
       // add-with-carry instead of a packed mask and a population count
       uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (!PAY) {
+      if (ZT && zt) {
+        // high words of the offsets (odd 32-bit words of B), 32-bit compares
+        const uint32_t *a32 = (const uint32_t *)a + 1;
+        const uint32_t xw = (uint32_t)((uint64_t)x >> 32);
+        for (uint32_t d = 0; d < ml; d += 8) {
+          uint32_t y[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) y[u] = a32[2 * (d + u)];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) c[u] += (uint32_t)(y[u] < xw);
+        }
+      } else if (!PAY) {
         for (uint32_t d = 0; d < ml; d += 8) {
           K y[8];
 #pragma unroll
@@ -1774,7 +1802,8 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     }
     if (valid) {
       const uint32_t pos = isEq ? q : bs + rk;
-      const K out = dec_out ? Key<KT>::dec(x) : x;
+      const K xr = (ZT && zt) ? (K)(zmn + ((uint64_t)x >> zlsh)) : x;
+      const K out = dec_out ? Key<KT>::dec(xr) : xr;
       // keys-only: equal keys share a rank, so they all land on its first
       // position; every written position is marked (no return value, so the
       // store does not wait) and the positions left empty are filled below;
@@ -1786,9 +1815,12 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   }
   __syncthreads();
   if (!PAY) {
-    // An empty position p follows a run of equal keys of rank r < p - bs in
-    // its bucket; it receives the bucket's element of rank p - bs, the key x
-    // with #{y < x} <= p - bs < #{y <= x}, found by comparing all pairs.
+    // An empty position p follows a run of keys that tied at rank r < p - bs
+    // in their bucket (equal keys, or with offsets, equal high words); it
+    // receives the bucket's element of rank p - bs, the key x with
+    // #{y < x} <= p - bs < #{y <= x}, found by comparing all pairs exactly.
+    // The first empty position of a run also rewrites the run's first
+    // position, which holds whichever tied key got there last.
     for (uint32_t wi = tid; wi < nwb; wi += FIN_THREADS) {
       // bits b of word wi with b * nwb + wi < s
       const uint32_t nb = wi < s ? (s - wi + nwb - 1) / nwb : 0u;
@@ -1801,18 +1833,24 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         uint32_t id = 0;
         for (uint32_t span = 1u << ilog2c(NB); span; span >>= 1)
           if (id + span < NB && sm.bstart[id + span] <= p) id += span;
-        const uint32_t bs = sm.bstart[id], be = sm.bstart[id + 1], k = p - bs;
-        for (uint32_t j = bs; j < be; ++j) {
-          const K x = sm.B[j];
-          uint32_t lt = 0, le = 0;
-          for (uint32_t jj = bs; jj < be; ++jj) {
-            const K y = sm.B[jj];
-            lt += (uint32_t)(y < x);
-            le += (uint32_t)(y <= x);
-          }
-          if (lt <= k && k < le) {
-            dst[p] = dec_out ? Key<KT>::dec(x) : x;
-            break;
+        const uint32_t bs = sm.bstart[id], be = sm.bstart[id + 1];
+        const uint32_t pm = p - 1;  // > bs - 1: a bucket's first position is never empty
+        const bool redo = (sm.bm[pm % nwb] >> (pm / nwb)) & 1u;
+        for (uint32_t pp = redo ? pm : p; pp <= p; ++pp) {
+          const uint32_t k = pp - bs;
+          for (uint32_t j = bs; j < be; ++j) {
+            const K x = sm.B[j];
+            uint32_t lt = 0, le = 0;
+            for (uint32_t jj = bs; jj < be; ++jj) {
+              const K y = sm.B[jj];
+              lt += (uint32_t)(y < x);
+              le += (uint32_t)(y <= x);
+            }
+            if (lt <= k && k < le) {
+              const K xr = (ZT && zt) ? (K)(zmn + ((uint64_t)x >> zlsh)) : x;
+              dst[pp] = dec_out ? Key<KT>::dec(xr) : xr;
+              break;
+            }
           }
         }
       }

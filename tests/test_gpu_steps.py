@@ -161,3 +161,27 @@ def test_all_pairs_rank_definition_on_gpu(api):
     want = np.empty_like(keys)
     want[ranks] = keys
     assert np.array_equal(out, want)
+
+
+@pytest.mark.parametrize("spread", [1 << 40, 1 << 33, 1 << 20])
+def test_base_case_near_ties(api, spread):
+    # uint64 keys that differ only in their low bits inside a wide leaf: the
+    # ranking compares the high words of the keys' offsets, so such keys tie
+    # there and must still come out in exact order (and equal keys stay equal)
+    rng = np.random.default_rng([W.BASE_SEED, 93, spread.bit_length()])
+    n = 7500
+    centers = rng.integers(0, spread, size=60, dtype=np.uint64)
+    keys = centers[rng.integers(0, centers.size, size=n)] + rng.integers(0, 300, size=n, dtype=np.uint64)
+    keys[::7] = keys[1::7][: keys[::7].size]  # exact duplicates too
+    log("near ties spread=2^%d" % (spread.bit_length() - 1))
+    for flags in (0, 4):
+        p = api.make_params(base_cutoff=32, flags=flags)
+        out = to_host(api.sort_keys(to_dev(keys), params=p))
+        want, _ = oracle.oracle_sort(U64, keys)
+        assert np.array_equal(out, want), flags
+    big = np.concatenate([keys + np.uint64(i) * np.uint64(spread) for i in range(40)])
+    rng.shuffle(big)
+    p = api.make_params(levels=1, k=64, overpartition_b=2)
+    out = to_host(api.sort_keys(to_dev(big), params=p))
+    want, _ = oracle.oracle_sort(U64, big)
+    assert np.array_equal(out, want)
