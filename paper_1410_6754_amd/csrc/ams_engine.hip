@@ -398,8 +398,9 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
       K xs[CU];
 #pragma unroll
       for (uint32_t k = 0; k < CU / V; ++k) {
+        // whole offset in the vector operand, which the range check covers
         const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(
-            rs, tid * 16u, (base - lo) * (uint32_t)sizeof(K) + k * (256u * 16u), 0);
+            rs, tid * 16u + (base - lo) * (uint32_t)sizeof(K) + k * (256u * 16u), 0, 0);
         Vec16<K>::get(v, &xs[k * V]);
       }
       if (enc) {
@@ -1075,8 +1076,9 @@ AMS_DEV void sck_load(Rsrc rs, uint32_t coff, typename Key<KT>::T (&x)[KPT]) {
   static_assert(KPT % V == 0, "whole 16-byte loads per thread");
 #pragma unroll
   for (uint32_t k = 0; k < KPT / V; ++k) {
-    const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(rs, threadIdx.x * 16u,
-                                                          coff + k * (SCK_THREADS * 16u), 0);
+    // whole offset in the vector operand, which the range check covers
+    const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(
+        rs, threadIdx.x * 16u + coff + k * (SCK_THREADS * 16u), 0, 0);
     Vec16<K>::get(v, &x[k * V]);
   }
 }
@@ -1731,26 +1733,81 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   // ---- all-pairs rank inside every bucket, one slot of FIN_THREADS keys
   // per pass.  B is not modified while ranking, so every key goes straight
   // to its final position in dst once its rank is known.
-#pragma unroll 1
-  for (uint32_t k = 0; k < FIN_KPT; ++k) {
-    if (FIN_THREADS * k >= s) break;  // uniform: no key in this or later slots
+  struct RankSlot {
+    K x;
+    uint32_t bs, q, len, v;
+    bool valid, isEq;
+  };
+  // lane slot k: its bucket, its key and the length to scan
+  auto rank_slot = [&](uint32_t k) -> RankSlot {
+    RankSlot r;
     const uint32_t ps = tid + FIN_THREADS * k;
-    const bool valid = ps < s;
-    const uint32_t pv = valid ? ps : 0u;
+    r.valid = ps < s;
+    const uint32_t pv = r.valid ? ps : 0u;
     const uint32_t b = sm.bid[pv];
-    const bool isEq = eq && pv >= eqStart;  // equal keys: any arrangement is final
-    const uint32_t id = eq ? 2 * b + (isEq ? 1u : 0u) : b;
-    const uint32_t bs = sm.bstart[id];
+    r.isEq = eq && pv >= eqStart;  // equal keys: any arrangement is final
+    const uint32_t id = eq ? 2 * b + (r.isEq ? 1u : 0u) : b;
+    r.bs = sm.bstart[id];
     const uint32_t be = sm.bstart[id + 1];
-    const uint32_t q = bs + pv - lofs[id];
-    const K x = sm.B[q];
-    const uint32_t len = (valid && !isEq) ? be - bs : 0u;
-    const uint32_t v = PAY ? sm.vB[q] : 0u;
+    r.q = r.bs + pv - lofs[id];
+    r.x = sm.B[r.q];
+    r.len = (r.valid && !r.isEq) ? be - r.bs : 0u;
+    r.v = PAY ? sm.vB[r.q] : 0u;
+    return r;
+  };
+  auto emit = [&](const RankSlot &r, uint32_t rk) {
+    if (r.valid) {
+      const uint32_t pos = r.isEq ? r.q : r.bs + rk;
+      const K xr = (ZT && zt) ? (K)(zmn + ((uint64_t)r.x >> zlsh)) : r.x;
+      const K out = dec_out ? Key<KT>::dec(xr) : xr;
+      // keys-only: equal keys share a rank, so they all land on its first
+      // position; every written position is marked (no return value, so the
+      // store does not wait) and the positions left empty are filled below;
+      // a wavefront's marks hit different words and do not serialise
+      if (!PAY) atomicOr(&sm.bm[pos % nwb], 1u << (pos / nwb));
+      dst[pos] = out;
+      if (PAY) vdst[pos] = r.v;
+    }
+  };
+#pragma unroll 1
+  for (uint32_t k = 0; k < FIN_KPT;) {
+    if (FIN_THREADS * k >= s) break;  // uniform: no key in this or later slots
+    if (ZT && zt && padded && k + 1 < FIN_KPT) {
+      // offsets, two slots at a time so that their LDS reads overlap: high
+      // words (odd 32-bit words of B), 32-bit compares; both scans run to
+      // the longer trip count, which is safe past a bucket's end (later
+      // buckets and the pad hold larger high words)
+      const RankSlot r0 = rank_slot(k), r1 = rank_slot(k + 1);
+      const uint32_t ml = __builtin_amdgcn_readfirstlane(wave_max(r0.len > r1.len ? r0.len : r1.len));
+      const uint32_t *a0 = (const uint32_t *)(sm.B + r0.bs) + 1;
+      const uint32_t *a1 = (const uint32_t *)(sm.B + r1.bs) + 1;
+      const uint32_t x0 = (uint32_t)((uint64_t)r0.x >> 32), x1 = (uint32_t)((uint64_t)r1.x >> 32);
+      uint32_t c0[4] = {0, 0, 0, 0}, c1[4] = {0, 0, 0, 0};
+      for (uint32_t d = 0; d < ml; d += 8) {
+        uint32_t y0[8], y1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          y0[u] = a0[2 * (d + u)];
+          y1[u] = a1[2 * (d + u)];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          c0[u & 3] += (uint32_t)(y0[u] < x0);
+          c1[u & 3] += (uint32_t)(y1[u] < x1);
+        }
+      }
+      emit(r0, (c0[0] + c0[1]) + (c0[2] + c0[3]));
+      emit(r1, (c1[0] + c1[1]) + (c1[2] + c1[3]));
+      k += 2;
+      continue;
+    }
+    const RankSlot r = rank_slot(k);
+    const K x = r.x;
     // wave-uniform trip count, held in a scalar register
-    const uint32_t ml = __builtin_amdgcn_readfirstlane(wave_max(len));
+    const uint32_t ml = __builtin_amdgcn_readfirstlane(wave_max(r.len));
     uint32_t rk = 0;
     if (padded) {
-      const K *a = sm.B + bs;
+      const K *a = sm.B + r.bs;
       // one counter per unrolled element: each compare then feeds a single
       // add-with-carry instead of a packed mask and a population count
       uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1774,7 +1831,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
           for (int u = 0; u < 8; ++u) c[u] += (uint32_t)(y[u] < x);
         }
       } else {
-        const uint32_t qb = q - bs;  // j < q  <=>  d + u < qb
+        const uint32_t qb = r.q - r.bs;  // j < q  <=>  d + u < qb
         for (uint32_t d = 0; d < ml; d += 8) {
           K y[8];
 #pragma unroll
@@ -1791,27 +1848,17 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         uint32_t jj[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          jj[u] = d + u < len ? bs + d + u : q;
+          jj[u] = d + u < r.len ? r.bs + d + u : r.q;
           y[u] = sm.B[jj[u]];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          rk += (uint32_t)(d + u < len) &
-                ((uint32_t)(y[u] < x) | ((uint32_t)(y[u] == x) & (uint32_t)(jj[u] < q)));
+          rk += (uint32_t)(d + u < r.len) &
+                ((uint32_t)(y[u] < x) | ((uint32_t)(y[u] == x) & (uint32_t)(jj[u] < r.q)));
       }
     }
-    if (valid) {
-      const uint32_t pos = isEq ? q : bs + rk;
-      const K xr = (ZT && zt) ? (K)(zmn + ((uint64_t)x >> zlsh)) : x;
-      const K out = dec_out ? Key<KT>::dec(xr) : xr;
-      // keys-only: equal keys share a rank, so they all land on its first
-      // position; every written position is marked (no return value, so the
-      // store does not wait) and the positions left empty are filled below;
-      // a wavefront's marks hit different words and do not serialise
-      if (!PAY) atomicOr(&sm.bm[pos % nwb], 1u << (pos / nwb));
-      dst[pos] = out;
-      if (PAY) vdst[pos] = v;
-    }
+    emit(r, rk);
+    ++k;
   }
   __syncthreads();
   if (!PAY) {
@@ -2128,7 +2175,9 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     return AMS_EINVAL;
   }
   if (r * b > 2048) b = std::max<uint32_t>(1, 2048 / r);
-  uint32_t TC = (p && p->tile_keys) ? p->tile_keys : 32768;
+  // tiles of 64 Ki keys once there are at least 2048 of them (8 per CU):
+  // fewer per-tile histograms and tile starts to reduce and scan
+  uint32_t TC = (p && p->tile_keys) ? p->tile_keys : (keysBig >= (1ull << 27) ? 65536 : 32768);
   if (TC % 4096 || TC == 0) {
     set_error("tile_keys must be a positive multiple of 4096 (got %u)", TC);
     return AMS_EINVAL;

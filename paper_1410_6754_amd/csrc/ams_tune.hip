@@ -204,13 +204,14 @@ extern "C" ams_status ams_autotune(ams_key_t t, const void *d_kin, const uint32_
   cur.k = 256;
   cur.overpartition_b = 4;
   cur.base_cutoff = 32;
-  cur.tile_keys = 32768;
   double cur_ms = 0;
   if ((st = evaluate(cur, cur_ms))) return st;
-  {
+  {  // the levels and tile size the plan picked by itself
     Plan pl;
-    if (make_plan(pl, (int)t, pay, sizes.data(), (uint32_t)num, 0, &cur) == AMS_OK)
+    if (make_plan(pl, (int)t, pay, sizes.data(), (uint32_t)num, 0, &cur) == AMS_OK) {
       cur.levels = pl.L;
+      cur.tile_keys = pl.L ? pl.lev[0].TC : 32768;
+    }
   }
   const uint32_t Lauto = cur.levels;
   struct Dim {
@@ -221,12 +222,13 @@ extern "C" ams_status ams_autotune(ams_key_t t, const void *d_kin, const uint32_
       {&ams_params::k, {128, 512, 1024}},
       {&ams_params::overpartition_b, {2, 8}},
       {&ams_params::base_cutoff, {16, 24, 48}},
-      {&ams_params::tile_keys, {16384, 65536}},
+      {&ams_params::tile_keys, {16384, 32768, 65536}},
       {&ams_params::levels, {Lauto + 1, Lauto > 1 ? Lauto - 1 : Lauto + 2}},
   };
   for (const Dim &d : dims) {
     for (uint32_t v : d.values) {
       if (trials >= max_trials) break;
+      if (cur.*(d.field) == v) continue;
       ams_params cand = cur;
       cand.*(d.field) = v;
       if ((uint64_t)cand.k * cand.overpartition_b > 2048 || cand.levels > MAXLEV) continue;
