@@ -246,6 +246,16 @@ def main() -> int:
     kernels = {k: {"launches": v["launches"], "avg_ms": round(v["total_ms"] / v["launches"], 4),
                    "share": round(v["total_ms"] / sum(x["total_ms"] for x in per.values()), 4)}
                for k, v in sorted(per.items(), key=lambda kv: -kv[1]["total_ms"])}
+    # every HBM pass against the peak: the partition passes (count reads the
+    # keys, scatter reads and writes them) and the base case (reads and
+    # writes them once); algorithmic bytes per launch over its average time
+    passes = {}
+    for k in ("count", "scatter", "finish"):
+        if k in per:
+            am = per[k]["total_ms"] / per[k]["launches"]
+            gbs = alg_bytes[k] / (am * 1e-3) / 1e9
+            passes[k] = {"avg_launch_ms": round(am, 4), "algorithmic_bytes_per_launch": alg_bytes[k],
+                         "GB_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
     if args.trace_file:
         with open(args.trace_file, "w") as f:
             json.dump({"workload": args.workload, "trace": trace, "kernels": kernels}, f, indent=1)
@@ -276,6 +286,7 @@ def main() -> int:
                    "key": {W.KEY_U64: "uint64", W.KEY_U32: "uint32", W.KEY_F32: "float32"}[kt],
                    "payload": "uint32" if pay else None, "params": pkw},
         "roofline": roof,
+        "passes": passes,
         "cpu_baseline": cpu,
         "kernels": kernels,
         "verified_sorted": verified,

@@ -1733,6 +1733,9 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   // ---- all-pairs rank inside every bucket, one slot of FIN_THREADS keys
   // per pass.  B is not modified while ranking, so every key goes straight
   // to its final position in dst once its rank is known.
+  // slots ranked together on the offset path, and elements read per slot
+  // and trip
+  constexpr uint32_t RNS = 2, RNU = 8;
   struct RankSlot {
     K x;
     uint32_t bs, q, len, v;
@@ -1772,33 +1775,41 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
 #pragma unroll 1
   for (uint32_t k = 0; k < FIN_KPT;) {
     if (FIN_THREADS * k >= s) break;  // uniform: no key in this or later slots
-    if (ZT && zt && padded && k + 1 < FIN_KPT) {
-      // offsets, two slots at a time so that their LDS reads overlap: high
-      // words (odd 32-bit words of B), 32-bit compares; both scans run to
-      // the longer trip count, which is safe past a bucket's end (later
+    if (ZT && zt && padded && k + RNS <= FIN_KPT) {
+      // offsets, RNS slots at a time so that their LDS reads overlap: high
+      // words (odd 32-bit words of B), 32-bit compares; every scan runs to
+      // the longest trip count, which is safe past a bucket's end (later
       // buckets and the pad hold larger high words)
-      const RankSlot r0 = rank_slot(k), r1 = rank_slot(k + 1);
-      const uint32_t ml = __builtin_amdgcn_readfirstlane(wave_max(r0.len > r1.len ? r0.len : r1.len));
-      const uint32_t *a0 = (const uint32_t *)(sm.B + r0.bs) + 1;
-      const uint32_t *a1 = (const uint32_t *)(sm.B + r1.bs) + 1;
-      const uint32_t x0 = (uint32_t)((uint64_t)r0.x >> 32), x1 = (uint32_t)((uint64_t)r1.x >> 32);
-      uint32_t c0[4] = {0, 0, 0, 0}, c1[4] = {0, 0, 0, 0};
-      for (uint32_t d = 0; d < ml; d += 8) {
-        uint32_t y0[8], y1[8];
+      RankSlot r[RNS];
+      uint32_t lm = 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          y0[u] = a0[2 * (d + u)];
-          y1[u] = a1[2 * (d + u)];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          c0[u & 3] += (uint32_t)(y0[u] < x0);
-          c1[u & 3] += (uint32_t)(y1[u] < x1);
-        }
+      for (uint32_t j = 0; j < RNS; ++j) {
+        r[j] = rank_slot(k + j);
+        lm = r[j].len > lm ? r[j].len : lm;
       }
-      emit(r0, (c0[0] + c0[1]) + (c0[2] + c0[3]));
-      emit(r1, (c1[0] + c1[1]) + (c1[2] + c1[3]));
-      k += 2;
+      const uint32_t ml = __builtin_amdgcn_readfirstlane(wave_max(lm));
+      const uint32_t *a[RNS];
+      uint32_t xw[RNS], c[RNS][2];
+#pragma unroll
+      for (uint32_t j = 0; j < RNS; ++j) {
+        a[j] = (const uint32_t *)(sm.B + r[j].bs) + 1;
+        xw[j] = (uint32_t)((uint64_t)r[j].x >> 32);
+        c[j][0] = c[j][1] = 0;
+      }
+      for (uint32_t d = 0; d < ml; d += RNU) {
+        uint32_t y[RNS][RNU];
+#pragma unroll
+        for (uint32_t u = 0; u < RNU; ++u)
+#pragma unroll
+          for (uint32_t j = 0; j < RNS; ++j) y[j][u] = a[j][2 * (d + u)];
+#pragma unroll
+        for (uint32_t u = 0; u < RNU; ++u)
+#pragma unroll
+          for (uint32_t j = 0; j < RNS; ++j) c[j][u & 1] += (uint32_t)(y[j][u] < xw[j]);
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < RNS; ++j) emit(r[j], c[j][0] + c[j][1]);
+      k += RNS;
       continue;
     }
     const RankSlot r = rank_slot(k);
