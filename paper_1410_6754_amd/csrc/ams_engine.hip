@@ -1698,6 +1698,13 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   // bstart[id] + p - lofs[id].
   uint16_t *lofs = PAY ? (uint16_t *)sm.cnt : (uint16_t *)(sm.cnt + nwb);  // NB first slots
   uint32_t *hist = (uint32_t *)sm.srt;  // keys per class (cleared in the split); [64]: start of equality slots
+  // keys only, after hist in the same area: one flag byte per bucket whose
+  // keys tied in the ranking, then a word set when any bucket has one
+  constexpr uint32_t TIED_WORDS = 2 * FMAX / 4;
+  static_assert((68 + TIED_WORDS + 1) * 4 <= FMAX * sizeof(K), "tie flags fit the splitter area");
+  uint32_t *tiedw = hist + 68;
+  uint8_t *tied = (uint8_t *)tiedw;
+  uint32_t *anyTied = tiedw + TIED_WORDS;
   {
     const bool haveId = tid < NB;
     const bool eqId = eq && (tid & 1u);
@@ -1725,8 +1732,10 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       for (; j + 4 <= hi; j += 4) *(uint32_t *)(sm.bid + j) = word;
       for (; j < hi; ++j) sm.bid[j] = (uint8_t)bb;
     }
-    if (!PAY)
+    if (!PAY) {
       for (uint32_t w32 = tid; w32 < nwb; w32 += FIN_THREADS) sm.bm[w32] = 0;
+      for (uint32_t w32 = tid; w32 <= TIED_WORDS; w32 += FIN_THREADS) tiedw[w32] = 0;
+    }
     __syncthreads();
   }
   const uint32_t eqStart = hist[64];
@@ -1738,7 +1747,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   constexpr uint32_t RNS = 2, RNU = 8;
   struct RankSlot {
     K x;
-    uint32_t bs, q, len, v;
+    uint32_t id, bs, q, len, v;
     bool valid, isEq;
   };
   // lane slot k: its bucket, its key and the length to scan
@@ -1750,6 +1759,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     const uint32_t b = sm.bid[pv];
     r.isEq = eq && pv >= eqStart;  // equal keys: any arrangement is final
     const uint32_t id = eq ? 2 * b + (r.isEq ? 1u : 0u) : b;
+    r.id = id;
     r.bs = sm.bstart[id];
     const uint32_t be = sm.bstart[id + 1];
     r.q = r.bs + pv - lofs[id];
@@ -1873,12 +1883,9 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   }
   __syncthreads();
   if (!PAY) {
-    // An empty position p follows a run of keys that tied at rank r < p - bs
-    // in their bucket (equal keys, or with offsets, equal high words); it
-    // receives the bucket's element of rank p - bs, the key x with
-    // #{y < x} <= p - bs < #{y <= x}, found by comparing all pairs exactly.
-    // The first empty position of a run also rewrites the run's first
-    // position, which holds whichever tied key got there last.
+    // An empty position follows a run of keys that tied at one rank in
+    // their bucket (equal keys or, with offsets, equal high words): flag
+    // the buckets that hold empty positions.
     for (uint32_t wi = tid; wi < nwb; wi += FIN_THREADS) {
       // bits b of word wi with b * nwb + wi < s
       const uint32_t nb = wi < s ? (s - wi + nwb - 1) / nwb : 0u;
@@ -1891,25 +1898,31 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         uint32_t id = 0;
         for (uint32_t span = 1u << ilog2c(NB); span; span >>= 1)
           if (id + span < NB && sm.bstart[id + span] <= p) id += span;
-        const uint32_t bs = sm.bstart[id], be = sm.bstart[id + 1];
-        const uint32_t pm = p - 1;  // > bs - 1: a bucket's first position is never empty
-        const bool redo = (sm.bm[pm % nwb] >> (pm / nwb)) & 1u;
-        for (uint32_t pp = redo ? pm : p; pp <= p; ++pp) {
-          const uint32_t k = pp - bs;
-          for (uint32_t j = bs; j < be; ++j) {
-            const K x = sm.B[j];
-            uint32_t lt = 0, le = 0;
-            for (uint32_t jj = bs; jj < be; ++jj) {
-              const K y = sm.B[jj];
-              lt += (uint32_t)(y < x);
-              le += (uint32_t)(y <= x);
-            }
-            if (lt <= k && k < le) {
-              const K xr = (ZT && zt) ? (K)(zmn + ((uint64_t)x >> zlsh)) : x;
-              dst[pp] = dec_out ? Key<KT>::dec(xr) : xr;
-              break;
-            }
+        tied[id] = 1;
+        *anyTied = 1;
+      }
+    }
+    __syncthreads();
+    if (*anyTied) {
+      // The keys of flagged buckets are ranked again with the full keys,
+      // ties broken by position in B, which gives every key its own
+      // position; all of the bucket is written again.  The first writes
+      // must be complete before the second ones are issued.
+      __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+#pragma unroll 1
+      for (uint32_t k = 0; k < FIN_KPT; ++k) {
+        if (FIN_THREADS * k >= s) break;
+        const RankSlot r = rank_slot(k);
+        if (r.valid && !r.isEq && tied[r.id]) {
+          const uint32_t qb = r.q - r.bs;
+          uint32_t rk = 0;
+          for (uint32_t j = 0; j < r.len; ++j) {
+            const K y = sm.B[r.bs + j];
+            rk += (uint32_t)(y < r.x) | ((uint32_t)(y == r.x) & (uint32_t)(j < qb));
           }
+          const K xr = (ZT && zt) ? (K)(zmn + ((uint64_t)r.x >> zlsh)) : r.x;
+          dst[r.bs + rk] = dec_out ? Key<KT>::dec(xr) : xr;
         }
       }
     }

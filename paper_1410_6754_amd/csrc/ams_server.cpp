@@ -125,12 +125,13 @@ struct ams_server {
     return align256(r.n * kbytes(r.type)) + (r.vals ? align256(r.n * 4) : 0);
   }
 
-  // Called with mu held.  Forms and launches batches while a stream is free.
+  // Called with mu held through lk (released while a batch is launched).
+  // Forms and launches batches while a stream is free.
   // A batch takes the oldest pending requests of the head's key type and
   // payload, in FIFO order, while the result bytes plus a bound on the
   // workspace fit the budget; the exact plan is made once for the batch and
   // requests are dropped from its end if it does not fit.
-  void schedule() {
+  void schedule(std::unique_lock<std::mutex> &lk) {
     for (;;) {
       int free_s = -1;
       for (size_t i = 0; i < streams.size(); ++i)
@@ -168,7 +169,7 @@ struct ams_server {
         sizes.pop_back();
       }
       if (pick.empty()) return;  // not enough memory yet; retry when some frees
-      launch(free_s, type, pay, pick, sizes, ws, results);
+      launch(lk, free_s, type, pay, pick, sizes, ws, results);
     }
   }
 
@@ -179,8 +180,13 @@ struct ams_server {
     --outstanding;
   }
 
-  void launch(int si, ams_key_t type, bool pay, const std::vector<uint64_t> &pick,
-              const std::vector<uint64_t> &sizes, size_t ws_bytes, size_t results) {
+  // Called with mu held through lk.  The requests leave the queue and are
+  // marked running under the lock; the plan, the allocations and the
+  // launches run with the lock released, so that submits, polls and
+  // releases of other requests do not wait for them.
+  void launch(std::unique_lock<std::mutex> &lk, int si, ams_key_t type, bool pay,
+              const std::vector<uint64_t> &pick, const std::vector<uint64_t> &sizes,
+              size_t ws_bytes, size_t results) {
     StreamState &ss = streams[si];
     hipStream_t s = ss.s;
     Batch b;
@@ -201,6 +207,24 @@ struct ams_server {
         }
       }
     }
+    struct In {
+      const void *keys;
+      const uint32_t *vals;
+      uint64_t n;
+      void *out_k;
+      uint32_t *out_v;
+    };
+    std::vector<In> in(pick.size());
+    for (size_t i = 0; i < pick.size(); ++i) {
+      Request &r = reqs[pick[i]];
+      r.state = RUNNING;
+      r.st.t_admit_us = ta;
+      in[i] = In{r.keys, r.vals, r.n, nullptr, nullptr};
+    }
+    reserved += results + ws_bytes;
+    ss.busy = true;
+    lk.unlock();
+
     ams_status st = AMS_OK;
     ResultBlock blk;
     Plan pl;
@@ -219,10 +243,9 @@ struct ams_server {
       uint64_t off = 0;
       char *cur = (char *)blk.ptr;
       for (size_t i = 0; i < pick.size(); ++i) {
-        Request &r = reqs[pick[i]];
+        In &r = in[i];
         r.out_k = cur;
         cur += align256(r.n * kbytes(type));
-        r.out_v = nullptr;
         if (pay) {
           r.out_v = (uint32_t *)cur;
           cur += align256(r.n * 4);
@@ -250,30 +273,28 @@ struct ams_server {
       (void)hipEventRecord(ss.ev1, s);
     }
     const double tl = now_us(t0);
+
+    lk.lock();
     blk.live = (uint32_t)pick.size();
     if (blk.ptr) blocks[b.id] = blk;
-    reserved += results + ws_bytes;
-    for (uint64_t t : pick) {
-      Request &r = reqs[t];
-      r.st.t_admit_us = ta;
+    for (size_t i = 0; i < pick.size(); ++i) {
+      Request &r = reqs[pick[i]];
+      r.out_k = in[i].out_k;
+      r.out_v = in[i].out_v;
       r.st.t_launch_us = tl;
       r.st.batch_id = b.id;
       r.st.batch_size = (uint32_t)pick.size();
       r.result_bytes = carved(r);
-      if (st) {
-        fail(r, st);
-      } else {
-        r.state = RUNNING;
-      }
+      if (st) fail(r, st);
     }
     if (st) {
       (void)hipStreamSynchronize(s);
       finish_batch(b, false);
       reserved -= ws_bytes;
+      ss.busy = false;
       cv_done.notify_all();
       return;
     }
-    ss.busy = true;
     running.push_back(b);
   }
 
@@ -339,7 +360,7 @@ struct ams_server {
     std::unique_lock<std::mutex> lk(mu);
     while (!stop || !running.empty()) {
       if (reap()) cv_done.notify_all();
-      if (!stop) schedule();
+      if (!stop) schedule(lk);
       if (running.empty() && (queue.empty() || stop)) {
         cv_work.wait_for(lk, std::chrono::milliseconds(5));
       } else {

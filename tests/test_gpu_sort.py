@@ -55,6 +55,32 @@ def test_distributions_f32(api, dist):
 
 
 @pytest.mark.parametrize("kt", [U64, U32, F32])
+@pytest.mark.parametrize("distinct", [3, 40, 1000])
+def test_keys_only_dense_duplicates(api, kt, distinct):
+    """Keys-only leaves where most keys tie with others: equal keys share a
+    rank in the first ranking pass, and every bucket with such ties is ranked
+    again exactly; also normal float32 keys, whose values repeat once there
+    are a few million of them (the serving mix)."""
+    log("dense duplicates kt=%d distinct=%d" % (kt, distinct))
+    rng = np.random.default_rng([W.BASE_SEED, 900 + distinct + kt])
+    n = 300001
+    if kt == F32:
+        vals = np.round(rng.normal(0.0, 1.0, distinct) * 64.0) / 64.0
+        keys = rng.choice(vals.astype(np.float32), n)
+    else:
+        dt = np.uint64 if kt == U64 else np.uint32
+        pool = rng.integers(0, np.iinfo(dt).max, distinct, dtype=dt, endpoint=True)
+        keys = rng.choice(pool, n)
+    check_sort_keys(api, kt, keys, what="kt%d distinct%d" % (kt, distinct))
+
+
+def test_keys_only_normal_f32_repeats(api):
+    log("normal f32 with repeated values")
+    keys = gen(F32, 1 << 23, "uniform", 31)  # float32 keys are N(0, 1)
+    check_sort_keys(api, F32, keys, what="normal f32 2^23")
+
+
+@pytest.mark.parametrize("kt", [U64, U32, F32])
 @pytest.mark.parametrize("n", [1, 100, 8192, 50000])
 def test_pairs_stable(api, kt, n):
     log("pairs kt=%d n=%d" % (kt, n))
