@@ -1785,11 +1785,10 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
 #pragma unroll 1
   for (uint32_t k = 0; k < FIN_KPT;) {
     if (FIN_THREADS * k >= s) break;  // uniform: no key in this or later slots
-    if (ZT && zt && padded && k + RNS <= FIN_KPT) {
-      // offsets, RNS slots at a time so that their LDS reads overlap: high
-      // words (odd 32-bit words of B), 32-bit compares; every scan runs to
-      // the longest trip count, which is safe past a bucket's end (later
-      // buckets and the pad hold larger high words)
+    if (!PAY && padded && k + RNS <= FIN_KPT) {
+      // keys only, RNS slots at a time so that their LDS reads overlap;
+      // every scan runs to the longest trip count, which is safe past a
+      // bucket's end (later buckets and the pad hold larger values)
       RankSlot r[RNS];
       uint32_t lm = 0;
 #pragma unroll
@@ -1798,27 +1797,37 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         lm = r[j].len > lm ? r[j].len : lm;
       }
       const uint32_t ml = __builtin_amdgcn_readfirstlane(wave_max(lm));
-      const uint32_t *a[RNS];
-      uint32_t xw[RNS], c[RNS][2];
+      // T: the compared word, the high 32 bits of an offset (odd 32-bit
+      // words of B) or the whole key
+      auto scan = [&](auto tag) {
+        typedef decltype(tag) T;
+        constexpr uint32_t STEP = (uint32_t)(sizeof(K) / sizeof(T));
+        const T *a[RNS];
+        T xw[RNS];
+        uint32_t c[RNS][2];
 #pragma unroll
-      for (uint32_t j = 0; j < RNS; ++j) {
-        a[j] = (const uint32_t *)(sm.B + r[j].bs) + 1;
-        xw[j] = (uint32_t)((uint64_t)r[j].x >> 32);
-        c[j][0] = c[j][1] = 0;
-      }
-      for (uint32_t d = 0; d < ml; d += RNU) {
-        uint32_t y[RNS][RNU];
+        for (uint32_t j = 0; j < RNS; ++j) {
+          a[j] = (const T *)(sm.B + r[j].bs) + (STEP - 1);
+          if constexpr (sizeof(T) < sizeof(K)) xw[j] = (T)((uint64_t)r[j].x >> 32);
+          else xw[j] = (T)r[j].x;
+          c[j][0] = c[j][1] = 0;
+        }
+        for (uint32_t d = 0; d < ml; d += RNU) {
+          T y[RNS][RNU];
 #pragma unroll
-        for (uint32_t u = 0; u < RNU; ++u)
+          for (uint32_t u = 0; u < RNU; ++u)
 #pragma unroll
-          for (uint32_t j = 0; j < RNS; ++j) y[j][u] = a[j][2 * (d + u)];
+            for (uint32_t j = 0; j < RNS; ++j) y[j][u] = a[j][STEP * (d + u)];
 #pragma unroll
-        for (uint32_t u = 0; u < RNU; ++u)
+          for (uint32_t u = 0; u < RNU; ++u)
 #pragma unroll
-          for (uint32_t j = 0; j < RNS; ++j) c[j][u & 1] += (uint32_t)(y[j][u] < xw[j]);
-      }
+            for (uint32_t j = 0; j < RNS; ++j) c[j][u & 1] += (uint32_t)(y[j][u] < xw[j]);
+        }
 #pragma unroll
-      for (uint32_t j = 0; j < RNS; ++j) emit(r[j], c[j][0] + c[j][1]);
+        for (uint32_t j = 0; j < RNS; ++j) emit(r[j], c[j][0] + c[j][1]);
+      };
+      if (ZT && zt) scan(uint32_t{});
+      else scan(K{});
       k += RNS;
       continue;
     }
