@@ -74,6 +74,20 @@ def test_keys_only_dense_duplicates(api, kt, distinct):
     check_sort_keys(api, kt, keys, what="kt%d distinct%d" % (kt, distinct))
 
 
+@pytest.mark.parametrize("hibits", [12, 20, 28])
+@pytest.mark.parametrize("n", [300001, 3000001])
+def test_u64_shared_high_words(api, hibits, n):
+    """uint64 keys whose high 32-bit words take few values: the partition
+    levels classify on high words first and must redo, on the full keys,
+    every wavefront holding a key whose high word equals a splitter's."""
+    log("shared high words hibits=%d n=%d" % (hibits, n))
+    rng = np.random.default_rng([W.BASE_SEED, 950 + hibits])
+    # 2^hibits distinct high words spread over the 32-bit range, random low words
+    hi = rng.integers(0, 1 << hibits, n, dtype=np.uint64) << np.uint64(64 - hibits)
+    keys = hi | rng.integers(0, 1 << 32, n, dtype=np.uint64)
+    check_sort_keys(api, U64, keys, what="hibits%d n%d" % (hibits, n))
+
+
 def test_keys_only_normal_f32_repeats(api):
     log("normal f32 with repeated values")
     keys = gen(F32, 1 << 23, "uniform", 31)  # float32 keys are N(0, 1)
