@@ -57,8 +57,11 @@ typedef int ams_status;
 #define AMS_EUNSUPPORTED (-5) /* size or option outside what this build supports */
 #define AMS_ENOTFOUND (-6)    /* server: unknown or released ticket */
 
-/* Tuning parameters.  A zero field means "choose automatically" (the built-in
- * autotuned defaults); passing NULL means all defaults.  Names follow the
+/* Tuning parameters.  A zero field means "choose automatically": the
+ * autotuner's choice for the call's shape class when ams_autotune has made
+ * one, else the built-in defaults (k = 256, b = 4 for one sort; k = 128,
+ * b = 2 for a batch of several segments; cutoff 32; tiles of 64 Ki keys from
+ * 2^27 keys, else 32 Ki); passing NULL means all defaults.  Names follow the
  * paper: k is the number of groups per level (the paper's r), b the
  * overpartitioning factor, a the oversampling factor (Section 6). */
 typedef struct {

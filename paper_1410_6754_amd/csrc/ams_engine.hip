@@ -2197,12 +2197,15 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
   pl.cutoff = (p && p->base_cutoff) ? std::min<uint32_t>(std::max<uint32_t>(p->base_cutoff, 2), 1024) : 32;
   pl.seed = (p && p->seed) ? p->seed : 14106754ull;
   pl.flags = p ? p->flags : 0;
-  uint32_t r = (p && p->k) ? p->k : 256;
+  // defaults: r = 256, b = 4 for one sort; r = 128, b = 2 for a batch, where
+  // subproblems are smaller and fewer buckets cost less per level
+  const bool batch = nroots > 1;
+  uint32_t r = (p && p->k) ? p->k : (batch ? 128 : 256);
   if (r < 2 || r > 1024 || (r & (r - 1))) {
     set_error("k must be a power of two in 2..1024 (got %u)", r);
     return AMS_EINVAL;
   }
-  uint32_t b = (p && p->overpartition_b) ? p->overpartition_b : 4;
+  uint32_t b = (p && p->overpartition_b) ? p->overpartition_b : (batch ? 2 : 4);
   if (b < 1 || (b & (b - 1))) {
     set_error("overpartition_b must be a power of two (got %u)", b);
     return AMS_EINVAL;
