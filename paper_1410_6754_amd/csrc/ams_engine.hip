@@ -1804,9 +1804,10 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
         constexpr uint32_t STEP = (uint32_t)(sizeof(K) / sizeof(T));
         const T *a[RNS];
         T xw[RNS];
-        uint32_t c[RNS][2];
+        uint32_t c[RNS][2], qb[RNS];
 #pragma unroll
         for (uint32_t j = 0; j < RNS; ++j) {
+          qb[j] = r[j].q - r[j].bs;  // the key's own position in its bucket
           a[j] = (const T *)(sm.B + r[j].bs) + (STEP - 1);
           if constexpr (sizeof(T) < sizeof(K)) xw[j] = (T)((uint64_t)r[j].x >> 32);
           else xw[j] = (T)r[j].x;
@@ -1818,10 +1819,21 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
           for (uint32_t u = 0; u < RNU; ++u)
 #pragma unroll
             for (uint32_t j = 0; j < RNS; ++j) y[j][u] = a[j][STEP * (d + u)];
+          if constexpr (sizeof(K) == 4) {
+            // 32-bit keys repeat often: equal keys are ordered by their
+            // position in B here, so no position is left empty
 #pragma unroll
-          for (uint32_t u = 0; u < RNU; ++u)
+            for (uint32_t u = 0; u < RNU; ++u)
 #pragma unroll
-            for (uint32_t j = 0; j < RNS; ++j) c[j][u & 1] += (uint32_t)(y[j][u] < xw[j]);
+              for (uint32_t j = 0; j < RNS; ++j)
+                c[j][u & 1] += (uint32_t)(y[j][u] < xw[j]) |
+                               ((uint32_t)(y[j][u] == xw[j]) & (uint32_t)(d + u < qb[j]));
+          } else {
+#pragma unroll
+            for (uint32_t u = 0; u < RNU; ++u)
+#pragma unroll
+              for (uint32_t j = 0; j < RNS; ++j) c[j][u & 1] += (uint32_t)(y[j][u] < xw[j]);
+          }
         }
 #pragma unroll
         for (uint32_t j = 0; j < RNS; ++j) emit(r[j], c[j][0] + c[j][1]);
