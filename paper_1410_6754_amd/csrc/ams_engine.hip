@@ -1681,6 +1681,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       const uint32_t q = (PAY ? sm.cnt[wave * NB + id] : sm.bstart[id]) + (xir[k] & 0xFFFFu);
       sm.B[q] = (ZT && zt) ? (K)((xk[k] - zmn) << zlsh) : xk[k];
       if (PAY) sm.vB[q] = xv[k];
+      if (!PAY && !eq) sm.bid[q] = (uint8_t)id;  // direct order: ids < f <= 256
     }
   }
   if (s + Lb + 8 <= C + FIN_PAD)
@@ -1688,6 +1689,11 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   __syncthreads();
   // scans of at most Lb + 7 slots past a bucket start stay inside B
   const bool padded = s + Lb + 8 <= C + FIN_PAD;
+  // Direct order (keys only, no equality buckets): lane slot p ranks the key
+  // at B position p, whose bucket id the placement wrote to bid[p].  The
+  // buckets of one split are about equally long, so a wavefront's trip
+  // count is close to its lanes' own without regrouping them.
+  const bool direct = !PAY && !eq;
   // ---- work order.  A wavefront ranks its keys in a common trip count,
   // the longest bucket among its lanes, so the keys are handed to lanes
   // bucket by bucket in order of decreasing bucket size (64 size classes):
@@ -1705,7 +1711,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   uint32_t *tiedw = hist + 68;
   uint8_t *tied = (uint8_t *)tiedw;
   uint32_t *anyTied = tiedw + TIED_WORDS;
-  {
+  if (!direct) {
     const bool haveId = tid < NB;
     const bool eqId = eq && (tid & 1u);
     uint32_t L = 0, cls = 0, kslot = 0;
@@ -1732,13 +1738,13 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       for (; j + 4 <= hi; j += 4) *(uint32_t *)(sm.bid + j) = word;
       for (; j < hi; ++j) sm.bid[j] = (uint8_t)bb;
     }
-    if (!PAY) {
-      for (uint32_t w32 = tid; w32 < nwb; w32 += FIN_THREADS) sm.bm[w32] = 0;
-      for (uint32_t w32 = tid; w32 <= TIED_WORDS; w32 += FIN_THREADS) tiedw[w32] = 0;
-    }
-    __syncthreads();
   }
-  const uint32_t eqStart = hist[64];
+  if (!PAY) {
+    for (uint32_t w32 = tid; w32 < nwb; w32 += FIN_THREADS) sm.bm[w32] = 0;
+    for (uint32_t w32 = tid; w32 <= TIED_WORDS; w32 += FIN_THREADS) tiedw[w32] = 0;
+  }
+  __syncthreads();
+  const uint32_t eqStart = direct ? s : hist[64];
   // ---- all-pairs rank inside every bucket, one slot of FIN_THREADS keys
   // per pass.  B is not modified while ranking, so every key goes straight
   // to its final position in dst once its rank is known.
@@ -1762,7 +1768,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     r.id = id;
     r.bs = sm.bstart[id];
     const uint32_t be = sm.bstart[id + 1];
-    r.q = r.bs + pv - lofs[id];
+    r.q = direct ? pv : r.bs + pv - lofs[id];
     r.x = sm.B[r.q];
     r.len = (r.valid && !r.isEq) ? be - r.bs : 0u;
     r.v = PAY ? sm.vB[r.q] : 0u;
