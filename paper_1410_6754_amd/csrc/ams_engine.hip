@@ -1750,7 +1750,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   // to its final position in dst once its rank is known.
   // slots ranked together on the offset path, and elements read per slot
   // and trip
-  constexpr uint32_t RNS = 2, RNU = 8;
+  constexpr uint32_t RNS = 3, RNU = 4;
   struct RankSlot {
     K x;
     uint32_t id, bs, q, len, v;
