@@ -54,7 +54,7 @@ typedef int ams_status;
 #define AMS_ENOMEM (-2)       /* workspace too small / allocation failed / request can never fit */
 #define AMS_EHIP (-3)         /* a HIP runtime call failed */
 #define AMS_EAGAIN (-4)       /* server: pending queue full, try again */
-#define AMS_EUNSUPPORTED (-5) /* size or option outside what this build supports */
+#define AMS_EUNSUPPORTED (-5) /* size or option outside what the library supports */
 #define AMS_ENOTFOUND (-6)    /* server: unknown or released ticket */
 
 /* Tuning parameters.  A zero field means "choose automatically": the

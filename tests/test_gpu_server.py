@@ -94,3 +94,42 @@ def test_memory_budget_serialises_but_completes(api):
             want, _ = oracle.oracle_sort(W.KEY_U64, keys)
             assert np.array_equal(to_host(srv.result(t)), want)
             srv.release(t)
+
+
+def test_concurrent_submit_poll_release(api):
+    """Several host threads submit, poll, wait and release while the
+    scheduler launches batches with its lock released: every result equals
+    the oracle, and nothing is lost or answered twice."""
+    import threading
+    from paper_1410_6754_amd.server import Server
+    errors = []
+
+    def client(srv, cid):
+        try:
+            rng = np.random.default_rng([W.BASE_SEED, 300 + cid])
+            mine = []
+            for j in range(12):
+                n = int(2 ** rng.uniform(6, 16))
+                kt = [W.KEY_U64, W.KEY_U32, W.KEY_F32][j % 3]
+                keys = gen(kt, n, "uniform", 1000 * cid + j)
+                mine.append((srv.submit(to_dev(keys)), kt, keys))
+                srv.poll(mine[-1][0])
+            for t, kt, keys in mine:
+                srv.wait(t)
+                want, _ = oracle.oracle_sort(kt, keys)
+                got = to_host(srv.result(t))
+                if not np.array_equal(got.view(np.uint32) if got.dtype == np.float32 else got,
+                                      want.view(np.uint32) if want.dtype == np.float32 else want):
+                    errors.append("client %d: wrong result for %d keys" % (cid, keys.size))
+                srv.release(t)
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append("client %d: %r" % (cid, e))
+
+    with Server(streams=2) as srv:
+        threads = [threading.Thread(target=client, args=(srv, c)) for c in range(4)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(120)
+        assert not any(th.is_alive() for th in threads), "a client did not finish"
+    assert not errors, errors
