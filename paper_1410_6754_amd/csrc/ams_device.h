@@ -100,6 +100,12 @@ AMS_DEV uint32_t draw_pos(uint64_t state, uint32_t i, uint32_t n) {
 // with full-width instructions.  The resource and the byte offsets are
 // wave-uniform (scalar registers); each lane adds its own offset.
 // ---------------------------------------------------------------------------
+// An object in global memory.  Accesses through GMem<T> pointers compile to
+// global_* instructions, which count only in vmcnt; flat ones (what generic
+// pointers loaded from memory become) also count in lgkmcnt, so a wait for
+// an LDS result would also wait for every flat access in flight.
+template <typename T> using GMem = __attribute__((address_space(1))) T;
+
 typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 

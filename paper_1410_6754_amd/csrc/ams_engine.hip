@@ -258,7 +258,7 @@ template <int KT> __global__ void __launch_bounds__(256) k_sample_blocks(Ws w, L
     uint32_t buf = seg_buf(s.meta);
     const K *src = kptr<K>(w, R, buf) + s.off;
     uint64_t st = stream_state(lv.seed, lv.level, s.root, s.off);
-    K x = src[draw_pos(st, j * 256 + tid, s.size)];
+    K x = ((const GMem<K> *)src)[draw_pos(st, j * 256 + tid, s.size)];
     if (buf == BUF_IN) x = Key<KT>::enc(x);
     sh[tid] = x;
     __syncthreads();
@@ -962,8 +962,8 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
     for (uint32_t c = tid; c < nch; c += 256) sBase[c] = w.tileOff[(size_t)g * CH + c];
     Root R = w.roots[s.root];
     const uint32_t buf = seg_buf(s.meta);
-    const K *src = kptr<K>(w, R, buf) + s.off;
-    const uint32_t *vsrc = PAY ? vptr(w, R, buf) + s.off : nullptr;
+    const GMem<K> *src = (const GMem<K> *)(kptr<K>(w, R, buf) + s.off);
+    const GMem<uint32_t> *vsrc = PAY ? (const GMem<uint32_t> *)(vptr(w, R, buf) + s.off) : nullptr;
     const bool enc = buf == BUF_IN;
     const uint32_t lo = t * lv.TC;
     const uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
@@ -1045,8 +1045,8 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
         const uint32_t db = cd & 15u;
         K x = stK[q];
         if (cd >> 4) x = Key<KT>::dec(x);
-        kptr<K>(w, R, db)[d] = x;
-        if (PAY) vptr(w, R, db)[d] = stV[q];
+        ((GMem<K> *)kptr<K>(w, R, db))[d] = x;
+        if (PAY) ((GMem<uint32_t> *)vptr(w, R, db))[d] = stV[q];
       }
       __syncthreads();
       for (uint32_t c = tid; c < nch; c += 256) sBase[c] += sTot[c];
@@ -1244,7 +1244,7 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
         const uint64_t d = q < cnt ? sDst[cc[k]] : 0ull;
         if (d) {
           const K x = (d & 1u) ? Key<KT>::dec(xo[k]) : xo[k];
-          *(K *)((d & ~(uint64_t)1) + (uint64_t)q * sizeof(K)) = x;
+          *(GMem<K> *)((d & ~(uint64_t)1) + (uint64_t)q * sizeof(K)) = x;
         }
       }
       // no barrier here: every wavefront finishes this write-out before it
@@ -1417,10 +1417,16 @@ AMS_DEV uint32_t leaf_loga(uint32_t logf) { return logf <= 6 ? 2u : 8u - logf; }
 
 template <int KT, bool PAY>
 AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
-                      const typename Key<KT>::T *src, const uint32_t *vsrc, bool enc_in,
-                      typename Key<KT>::T *dst, uint32_t *vdst, bool dec_out, uint32_t s,
+                      const typename Key<KT>::T *src_, const uint32_t *vsrc_, bool enc_in,
+                      typename Key<KT>::T *dst_, uint32_t *vdst_, bool dec_out, uint32_t s,
                       uint32_t C, uint32_t cutoff, uint64_t st, bool sampled_only) {
   typedef typename Key<KT>::T K;
+  // global views of the leaf's buffers: global (not flat) loads and stores
+  // count only in vmcnt, so the LDS waits of the ranking never wait for them
+  const GMem<K> *src = (const GMem<K> *)src_;
+  const GMem<uint32_t> *vsrc = (const GMem<uint32_t> *)vsrc_;
+  GMem<K> *dst = (GMem<K> *)dst_;
+  GMem<uint32_t> *vdst = (GMem<uint32_t> *)vdst_;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t f = leaf_fanout(s, cutoff);
   const uint32_t logf = ilog2c(f);
@@ -1960,10 +1966,14 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
 // Stable merge of sorted A[0..na) and B[0..nb) (A first on ties) into out,
 // split across the workgroup by output position (merge path).
 template <int KT, bool PAY>
-AMS_DEV void wg_merge(const typename Key<KT>::T *A, const uint32_t *vA, uint32_t na,
-                      const typename Key<KT>::T *B, const uint32_t *vB, uint32_t nb,
-                      typename Key<KT>::T *out, uint32_t *vout, bool dec_out) {
+AMS_DEV void wg_merge(const typename Key<KT>::T *A_, const uint32_t *vA_, uint32_t na,
+                      const typename Key<KT>::T *B_, const uint32_t *vB_, uint32_t nb,
+                      typename Key<KT>::T *out_, uint32_t *vout_, bool dec_out) {
   typedef typename Key<KT>::T K;
+  const GMem<K> *A = (const GMem<K> *)A_, *B = (const GMem<K> *)B_;
+  const GMem<uint32_t> *vA = (const GMem<uint32_t> *)vA_, *vB = (const GMem<uint32_t> *)vB_;
+  GMem<K> *out = (GMem<K> *)out_;
+  GMem<uint32_t> *vout = (GMem<uint32_t> *)vout_;
   const uint32_t len = na + nb;
   const uint32_t per = (len + FIN_THREADS - 1) / FIN_THREADS;
   const uint32_t k0 = threadIdx.x * per < len ? threadIdx.x * per : len;
@@ -2018,8 +2028,8 @@ __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint3
     uint32_t *vdst = PAY ? R.vout + L.off : nullptr;
     if (kind == LEAF_COPY) {
       for (uint32_t q = tid; q < L.size; q += FIN_THREADS) {
-        dst[q] = Key<KT>::dec(src[q]);
-        if (PAY) vdst[q] = vsrc[q];
+        ((GMem<K> *)dst)[q] = Key<KT>::dec(((const GMem<K> *)src)[q]);
+        if (PAY) ((GMem<uint32_t> *)vdst)[q] = ((const GMem<uint32_t> *)vsrc)[q];
       }
       continue;
     }
