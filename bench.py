@@ -205,15 +205,23 @@ def main() -> int:
     t0 = time.perf_counter()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    # an event between consecutive steps as well, for the spread of step times
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     ev0.record(stream)
-    for _ in range(args.steps):
+    marks[0].record(stream)
+    for i in range(args.steps):
         step()
+        marks[i + 1].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     trace = api.trace_stop()
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = gpu_ms / args.steps
+    steps_ms = np.array([marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)])
+    step_stats = {"min": round(float(steps_ms.min()), 4),
+                  "median": round(float(np.median(steps_ms)), 4),
+                  "p90": round(float(np.percentile(steps_ms, 90)), 4)}
     print("bench: timed %d steps, %.3f ms/step (wall %.3f s)" % (args.steps, ms_per_step, wall),
           file=sys.stderr, flush=True)
 
@@ -256,6 +264,16 @@ def main() -> int:
             gbs = alg_bytes[k] / (am * 1e-3) / 1e9
             passes[k] = {"avg_launch_ms": round(am, 4), "algorithmic_bytes_per_launch": alg_bytes[k],
                          "GB_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    if "count" in passes and "scatter" in passes:
+        # one partition level as a whole: count reads the keys, scatter reads
+        # and writes them (3w bytes per key moved by the implementation, of
+        # which 2w are the level's algorithmic read and write)
+        lm = passes["count"]["avg_launch_ms"] + passes["scatter"]["avg_launch_ms"]
+        ib = alg_bytes["count"] + alg_bytes["scatter"]
+        passes["partition_level"] = {
+            "ms": round(lm, 4), "implementation_bytes": ib,
+            "GB_per_s": round(ib / (lm * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(ib / (lm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if args.trace_file:
         with open(args.trace_file, "w") as f:
             json.dump({"workload": args.workload, "trace": trace, "kernels": kernels}, f, indent=1)
@@ -277,6 +295,7 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "step_ms": step_stats,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
