@@ -2247,8 +2247,12 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     return AMS_EINVAL;
   }
   const uint32_t Scap = 65536 / pl.kw;
-  // levels: enough that an average group fills at most 55% of the leaf
-  // capacity; the rest absorbs the imbalance of the grouping at each level
+  // levels: enough that an average group of the largest segment fills at
+  // most 55% of the leaf capacity (the rest absorbs the imbalance of the
+  // grouping at each level); for a batch, at most 120%: its few largest
+  // segments then send some groups to the merge fallback, which costs less
+  // than another level over all segments
+  const double fill = batch ? 1.2 : 0.55;
   uint32_t L = 0;
   if (mx > C) {
     if (p && p->levels) {
@@ -2256,7 +2260,7 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     } else {
       L = 1;
       double cap = (double)r;
-      while (L < MAXLEV && (double)mx / cap > 0.55 * C) {
+      while (L < MAXLEV && (double)mx / cap > fill * C) {
         ++L;
         cap *= r;
       }
