@@ -1687,7 +1687,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       const uint32_t q = (PAY ? sm.cnt[wave * NB + id] : sm.bstart[id]) + (xir[k] & 0xFFFFu);
       sm.B[q] = (ZT && zt) ? (K)((xk[k] - zmn) << zlsh) : xk[k];
       if (PAY) sm.vB[q] = xv[k];
-      if (!PAY && !eq) sm.bid[q] = (uint8_t)id;  // direct order: ids < f <= 256
+      if (!eq) sm.bid[q] = (uint8_t)id;  // direct order: ids < f <= 256
     }
   }
   if (s + Lb + 8 <= C + FIN_PAD)
@@ -1695,11 +1695,11 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   __syncthreads();
   // scans of at most Lb + 7 slots past a bucket start stay inside B
   const bool padded = s + Lb + 8 <= C + FIN_PAD;
-  // Direct order (keys only, no equality buckets): lane slot p ranks the key
-  // at B position p, whose bucket id the placement wrote to bid[p].  The
+  // Direct order (no equality buckets): lane slot p ranks the key at B
+  // position p, whose bucket id the placement wrote to bid[p].  The
   // buckets of one split are about equally long, so a wavefront's trip
   // count is close to its lanes' own without regrouping them.
-  const bool direct = !PAY && !eq;
+  const bool direct = !eq;
   // ---- work order.  A wavefront ranks its keys in a common trip count,
   // the longest bucket among its lanes, so the keys are handed to lanes
   // bucket by bucket in order of decreasing bucket size (64 size classes):
@@ -1797,10 +1797,10 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
 #pragma unroll 1
   for (uint32_t k = 0; k < FIN_KPT;) {
     if (FIN_THREADS * k >= s) break;  // uniform: no key in this or later slots
-    if (!PAY && padded && k + RNS <= FIN_KPT) {
-      // keys only, RNS slots at a time so that their LDS reads overlap;
-      // every scan runs to the longest trip count, which is safe past a
-      // bucket's end (later buckets and the pad hold larger values)
+    if (padded && k + RNS <= FIN_KPT) {
+      // RNS slots at a time so that their LDS reads overlap; every scan
+      // runs to the longest trip count, which is safe past a bucket's end
+      // (later buckets and the pad hold larger values)
       RankSlot r[RNS];
       uint32_t lm = 0;
 #pragma unroll
@@ -1831,9 +1831,10 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
           for (uint32_t u = 0; u < RNU; ++u)
 #pragma unroll
             for (uint32_t j = 0; j < RNS; ++j) y[j][u] = a[j][STEP * (d + u)];
-          if constexpr (sizeof(K) == 4) {
-            // 32-bit keys repeat often: equal keys are ordered by their
-            // position in B here, so no position is left empty
+          if constexpr (sizeof(K) == 4 || PAY) {
+            // 32-bit keys repeat often, and pairs must keep input order:
+            // equal keys are ordered by their position in B here (input
+            // order for pairs), so no position is left empty
 #pragma unroll
             for (uint32_t u = 0; u < RNU; ++u)
 #pragma unroll
