@@ -967,21 +967,31 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
     const bool enc = buf == BUF_IN;
     const uint32_t lo = t * lv.TC;
     const uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
-    for (uint32_t cb = lo; cb < hi; cb += CHK) {
-      for (uint32_t q = tid; q < 4 * CH; q += 256) sCnt[q] = 0;
-      __syncthreads();
-      K xk[KPT];
-      uint32_t xv[KPT];
-      uint32_t xcr[KPT];  // child << 16 | rank inside (wave, child)
+    // chunk keys (and payloads) at cb into registers; the next chunk of the
+    // tile is requested before the current one is classified
+    auto load_chunk = [&](uint32_t cb, K (&xk)[KPT], uint32_t (&xv)[KPT]) {
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
         const uint32_t p = cb + wave * (CHK / 4) + k * 64 + lane;
         const bool valid = p < hi;
-        K x = valid ? src[p] : (K)0;
-        if (enc) x = Key<KT>::enc(x);
-        xk[k] = x;
-        if (PAY) xv[k] = valid ? vsrc[p] : 0u;
+        xk[k] = valid ? src[p] : (K)0;
+        xv[k] = PAY && valid ? vsrc[p] : 0u;
       }
+    };
+    K xk[KPT];
+    uint32_t xv[KPT];
+    load_chunk(lo, xk, xv);
+    for (uint32_t cb = lo; cb < hi; cb += CHK) {
+      K nk[KPT];
+      uint32_t nv[KPT];
+      if (cb + CHK < hi) load_chunk(cb + CHK, nk, nv);
+      for (uint32_t q = tid; q < 4 * CH; q += 256) sCnt[q] = 0;
+      __syncthreads();
+      if (enc) {
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) xk[k] = Key<KT>::enc(xk[k]);
+      }
+      uint32_t xcr[KPT];  // child << 16 | rank inside (wave, child)
       classify_batch<K, KPT>(xk, xcr, sTree, gSpl, logm, eq);
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
@@ -1050,6 +1060,11 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
       }
       __syncthreads();
       for (uint32_t c = tid; c < nch; c += 256) sBase[c] += sTot[c];
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        xk[k] = nk[k];
+        xv[k] = nv[k];
+      }
     }
   }
 }
