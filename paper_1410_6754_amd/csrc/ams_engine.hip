@@ -1271,6 +1271,181 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
   }
 }
 
+// Pairs scatter with 1024 threads and chunks of 8192 pairs, so a child's run
+// in a chunk is four times longer than with k_scatter's 2048-pair chunks.
+// Wavefront v ranks the v-th sixteenth of the chunk in input order: ballots
+// rank lanes with equal children, and a row of 16-bit counters of its own
+// carries the rank from one row of keys to the next.  After the per-child
+// totals and offsets are formed, each wavefront clears its own row once it
+// has staged its keys, so the reset needs no barrier of its own.  The next
+// chunk of the tile is requested before the current one is classified.
+constexpr uint32_t SCP_KPT = 8;
+
+template <int KT>
+__global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_pairs(Ws w, Lev lv) {
+  typedef typename Key<KT>::T K;
+  constexpr uint32_t KPT = SCP_KPT, CHK = SCK_THREADS * KPT, NW = SCK_THREADS / 64;
+  constexpr uint32_t PW = CHK / NW;  // pairs per wavefront and chunk
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint32_t CH = lv.CH, CHP = (CH + 3) & ~3u;
+  K *sTree = (K *)smem_raw;                                  // mmax
+  K *stK = sTree + lv.mmax;                                  // CHK
+  uint32_t *stV = (uint32_t *)(stK + CHK);                   // CHK
+  uint16_t *stC = (uint16_t *)(stV + CHK);                   // CHK
+  uint16_t *sRow = stC + CHK;                                // NW rows of CHP counters
+  uint16_t *sI2C = sRow + NW * CHP;                          // HS (rounded up to even)
+  uint32_t *sBase = (uint32_t *)(sI2C + ((lv.HS + 1) & ~1u)); // CH
+  uint32_t *sL = sBase + CH;                                 // CH
+  uint32_t *sRel = sL + CH;                                  // CH: output index of slot 0
+  uint32_t *sTmp = sRel + CH;                                // NW
+  uint8_t *sCd = (uint8_t *)(sTmp + NW);                     // CH
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t P = w.ctr->P;
+  ItemRange ir = xcd_items(w.ctr->ntile);
+  uint32_t cur = 0xFFFFFFFFu, logm = 0, nch = 0, nbits = 0;
+  bool eq = false;
+  const K *gSpl = nullptr;
+  for (uint32_t q = tid; q < NW * CHP; q += SCK_THREADS) sRow[q] = 0;
+  uint16_t *row = sRow + wave * CHP;
+  for (uint32_t g = ir.first; g < ir.end; g += ir.step) {
+    const uint32_t i = find_owner(w.tileStart, P, g);
+    const uint32_t t = g - w.tileStart[i];
+    const Seg s = w.act[lv.level][i];
+    const Root R = w.roots[s.root];
+    if (i != cur) {
+      __syncthreads();
+      logm = meta_logm(s.meta);
+      const uint32_t m = 1u << logm;
+      const K *gt = (const K *)w.tree + (size_t)i * lv.mmax;
+      for (uint32_t j = tid + 1; j < m; j += SCK_THREADS) sTree[j] = gt[j];
+      eq = w.eqOn[i] != 0;
+      nch = w.nch[i];
+      nbits = ilog2c(nch);
+      const uint32_t NB = eq ? 2 * m - 1 : m;
+      const uint16_t *gi = w.i2c + (size_t)i * lv.HS;
+      for (uint32_t j = tid; j < NB; j += SCK_THREADS) sI2C[j] = gi[j];
+      const uint8_t *gd = w.cdst + (size_t)i * CH;
+      for (uint32_t c = tid; c < nch; c += SCK_THREADS) sCd[c] = gd[c];
+      gSpl = (const K *)w.spl + (size_t)i * lv.mmax;
+      cur = i;
+      __syncthreads();  // the subproblem's tables are in LDS
+    }
+    // sBase[c]: this tile's next output offset of child c (thread c only;
+    // nch <= CH <= 1024, so thread c owns child c)
+    if (tid < nch) sBase[tid] = w.tileOff[(size_t)g * CH + tid];
+    const uint32_t buf = seg_buf(s.meta);
+    const GMem<K> *src = (const GMem<K> *)(kptr<K>(w, R, buf) + s.off);
+    const GMem<uint32_t> *vsrc = (const GMem<uint32_t> *)(vptr(w, R, buf) + s.off);
+    const bool enc = buf == BUF_IN;
+    const uint32_t lo = t * lv.TC;
+    const uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
+    // keys are requested one chunk ahead; payloads at the start of their
+    // own chunk (they are needed only when the chunk is staged)
+    auto load_keys = [&](uint32_t cb, K (&xk)[KPT]) {
+#pragma unroll
+      for (uint32_t k = 0; k < KPT; ++k) {
+        const uint32_t p = cb + wave * PW + k * 64 + lane;
+        xk[k] = p < hi ? src[p] : (K)0;
+      }
+    };
+    K xk[KPT];
+    load_keys(lo, xk);
+    for (uint32_t cb = lo; cb < hi; cb += CHK) {
+      uint32_t xv[KPT];
+#pragma unroll
+      for (uint32_t k = 0; k < KPT; ++k) {
+        const uint32_t p = cb + wave * PW + k * 64 + lane;
+        xv[k] = p < hi ? vsrc[p] : 0u;
+      }
+      K nk[KPT];
+      if (cb + CHK < hi) load_keys(cb + CHK, nk);
+      if (enc) {
+#pragma unroll
+        for (uint32_t k = 0; k < KPT; ++k) xk[k] = Key<KT>::enc(xk[k]);
+      }
+      uint32_t xcr[KPT];  // child << 16 | rank among the wavefront's pairs of that child
+      classify_batch<K, KPT>(xk, xcr, sTree, gSpl, logm, eq);
+#pragma unroll
+      for (uint32_t k = 0; k < KPT; ++k) {
+        const bool valid = cb + wave * PW + k * 64 + lane < hi;
+        const uint32_t c = valid ? (uint32_t)sI2C[xcr[k]] : 0u;
+        const uint64_t peers = match_lanes(c, valid, nbits);
+        const uint32_t below = bits_below(peers);
+        uint32_t r = 0;
+        if (valid) {
+          r = row[c] + below;
+          if (below == 0) row[c] = (uint16_t)(r + (uint32_t)__popcll(peers));
+        }
+        xcr[k] = (c << 16) | r;
+      }
+      __syncthreads();
+      // per child: chunk total, its exclusive scan (sL), the offset of every
+      // wavefront's pairs (in the rows) and the output index of slot 0
+      const uint32_t c = tid;
+      uint32_t tot = 0;
+      if (c < nch) {
+#pragma unroll
+        for (uint32_t v = 0; v < NW; ++v) tot += sRow[v * CHP + c];
+        sL[c] = tot;
+      }
+      block_exscan<SCK_THREADS>(sL, nch, sTmp);  // thread c scans its own entry; ends on a barrier
+      if (c < nch) {
+        uint32_t run = sL[c];
+#pragma unroll
+        for (uint32_t v = 0; v < NW; ++v) {
+          const uint32_t n = sRow[v * CHP + c];
+          sRow[v * CHP + c] = (uint16_t)run;
+          run += n;
+        }
+        if ((uint64_t)sBase[c] + tot <= s.size) {
+          sRel[c] = s.off + sBase[c] - sL[c];
+        } else {  // would overrun the subproblem: dropped and flagged
+          atomicOr(&w.ctr->overflow, 16u);
+          sRel[c] = 0xFFFFFFFFu;
+        }
+        sBase[c] += tot;
+      }
+      __syncthreads();
+#pragma unroll
+      for (uint32_t k = 0; k < KPT; ++k) {
+        if (cb + wave * PW + k * 64 + lane < hi) {
+          const uint32_t cc = xcr[k] >> 16;
+          const uint32_t q = row[cc] + (xcr[k] & 0xFFFFu);
+          stK[q] = xk[k];
+          stV[q] = xv[k];
+          stC[q] = (uint16_t)cc;
+        }
+      }
+      // this wavefront's row is not read again in this chunk: clear it for
+      // the next one (CHP is a multiple of 4, rows are 8-byte aligned)
+      for (uint32_t j = lane; j < CHP / 4; j += 64) ((uint64_t *)row)[j] = 0;
+      __syncthreads();
+      // write out: consecutive slots of a child go to consecutive indices
+      const uint32_t cnt = hi - cb < CHK ? hi - cb : CHK;
+#pragma unroll
+      for (uint32_t k = 0; k < KPT; ++k) {
+        const uint32_t q = tid + SCK_THREADS * k;
+        if (q < cnt) {
+          const uint32_t cc = stC[q];
+          const uint32_t rel = sRel[cc];
+          if (rel != 0xFFFFFFFFu) {
+            const uint32_t cd = sCd[cc];
+            const uint32_t db = cd & 15u;
+            K x = stK[q];
+            if (cd >> 4) x = Key<KT>::dec(x);
+            ((GMem<K> *)kptr<K>(w, R, db))[rel + q] = x;
+            ((GMem<uint32_t> *)vptr(w, R, db))[rel + q] = stV[q];
+          }
+        }
+      }
+      // no barrier here: the next chunk writes the staging area and the
+      // per-child tables only after its first barrier
+#pragma unroll
+      for (uint32_t k = 0; k < KPT; ++k) xk[k] = nk[k];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Base case (Section 4.2 all-pairs ranking; Section 6 base case).
 // ---------------------------------------------------------------------------
@@ -2520,15 +2695,27 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
       hipLaunchKernelGGL((k_scatter<KT, false, KPT>), dim3(grid_for(ls.tiles, 512)), dim3(256),
                          ldsS, s, w, lv);
     } else if (PAY) {
-      constexpr int KPT = 8;
-      constexpr uint32_t CHK = 256 * KPT;
-      size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + CHK * 4 + CHK * 2 +
-                    (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + 4 + (size_t)ls.CH * 16 + 256 * 4 +
-                    ls.CH + 64;
-      allow_lds(k_scatter<KT, true, KPT>, ldsS);
+      // 8192-pair chunks when one thread per child and the LDS allow it
+      const size_t ldsP = (size_t)ls.mmax * sizeof(K) +
+                          (size_t)SCK_THREADS * SCP_KPT * (sizeof(K) + 4 + 2) +
+                          (size_t)(SCK_THREADS / 64) * ((ls.CH + 3) & ~3u) * 2 +
+                          (size_t)((ls.HS + 1) & ~1u) * 2 + (size_t)ls.CH * 4 * 3 +
+                          SCK_THREADS / 64 * 4 + ls.CH + 64;
       TraceScope ts("scatter", l, s);
-      hipLaunchKernelGGL((k_scatter<KT, true, KPT>), dim3(grid_for(ls.tiles, 512)), dim3(256),
-                         ldsS, s, w, lv);
+      if (ls.CH <= SCK_THREADS && ldsP <= 163840) {
+        allow_lds(k_scatter_pairs<KT>, ldsP);
+        hipLaunchKernelGGL(k_scatter_pairs<KT>, dim3(grid_for(ls.tiles, 512)), dim3(SCK_THREADS),
+                           ldsP, s, w, lv);
+      } else {
+        constexpr int KPT = 8;
+        constexpr uint32_t CHK = 256 * KPT;
+        size_t ldsS = (size_t)ls.mmax * sizeof(K) + CHK * sizeof(K) + CHK * 4 + CHK * 2 +
+                      (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + 4 + (size_t)ls.CH * 16 +
+                      256 * 4 + ls.CH + 64;
+        allow_lds(k_scatter<KT, true, KPT>, ldsS);
+        hipLaunchKernelGGL((k_scatter<KT, true, KPT>), dim3(grid_for(ls.tiles, 512)), dim3(256),
+                           ldsS, s, w, lv);
+      }
     } else {
       // chunks of 8192 keys, or 4096 when the tables of a wide level
       // (large k * b) leave too little LDS for the larger staging area
