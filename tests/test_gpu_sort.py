@@ -107,6 +107,20 @@ def test_pairs_hard_distributions(api):
         check_sort_pairs(api, U64, gen(U64, 200000, dist, 10), what=dist)
 
 
+# Forced plans that route pairs through both stable scatters: levels with at
+# most 1024 children whose tables fit next to an 8192-pair chunk use the
+# 1024-thread kernel; wider ones (k = 512 or 1024, or k * b = 2048 with
+# 64-bit keys) the 256-thread one.
+@pytest.mark.parametrize("kt", [U64, U32])
+@pytest.mark.parametrize("levels,k,b", [(1, 1024, 2), (1, 512, 2), (2, 256, 8), (2, 128, 2), (3, 16, 4)])
+def test_pairs_forced_level_plans(api, kt, levels, k, b):
+    n = 300001
+    log("pairs kt=%d levels=%d k=%d b=%d" % (kt, levels, k, b))
+    p = api.make_params(levels=levels, k=k, overpartition_b=b)
+    for dist in ["uniform", "few"]:
+        check_sort_pairs(api, kt, gen(kt, n, dist, 70 + k + levels), params=p, what=dist)
+
+
 def test_two_levels(api):
     n = (1 << 22) + 12345
     log("two levels n=%d" % n)
