@@ -1136,7 +1136,13 @@ AMS_DEV Rsrc tile_rsrc(const Ws &w, const Lev &lv, uint32_t P, uint32_t g) {
   return make_rsrc(uniform_ptr(src), __builtin_amdgcn_readfirstlane((hi - lo) * (uint32_t)sizeof(K)));
 }
 
-template <int KT, int KPT>
+// With PRIV (levels of at most SCK_PCH children) every wavefront scans the
+// chunk's child counts itself into a row of 16-bit offsets of its own, and
+// the counters alternate between two banks from chunk to chunk: a chunk then
+// needs two barriers instead of four.
+constexpr uint32_t SCK_PCH = 768;  // 12 children per lane
+
+template <int KT, int KPT, bool PRIV>
 __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
   typedef typename Key<KT>::T K;
   constexpr uint32_t CHK = SCK_THREADS * KPT;
@@ -1145,20 +1151,29 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
   K *sTree = (K *)smem_raw;                       // mmax
   K *stK = sTree + lv.mmax;                       // CHK
   uint64_t *sDst = (uint64_t *)(stK + CHK);       // CH: output address of chunk slot 0, per child
-  uint16_t *stC = (uint16_t *)(sDst + CH);        // CHK
+  // PRIV: two banks of SCK_PCH counters and 16 rows of SCK_PCH offsets
+  uint32_t *sCnt2 = (uint32_t *)(sDst + CH);
+  uint16_t *sRows = (uint16_t *)(sCnt2 + (PRIV ? 2 * SCK_PCH : 0));
+  uint16_t *stC = sRows + (PRIV ? (SCK_THREADS / 64) * SCK_PCH : 0);  // CHK
   uint16_t *sI2C = stC + CHK;                     // HS
   uint32_t *sBase = (uint32_t *)(sI2C + lv.HS);   // CH
-  uint32_t *sL = sBase + CH;                      // CH
-  uint32_t *sCnt = sL + CH;                       // CH
-  uint32_t *sTmp = sCnt + CH;                     // SCK_THREADS / 64
+  uint32_t *sL = sBase + CH;                      // CH (not PRIV)
+  uint32_t *sCnt = sL + (PRIV ? 0 : CH);          // CH (not PRIV)
+  uint32_t *sTmp = sCnt + (PRIV ? 0 : CH);        // SCK_THREADS / 64
   uint8_t *sCd = (uint8_t *)(sTmp + SCK_THREADS / 64);  // CH
   const uint32_t tid = threadIdx.x;
+  uint16_t *myRow = sRows + (tid >> 6) * SCK_PCH;
+  uint32_t par = 0;  // PRIV: counter bank of the current chunk
   const uint32_t P = w.ctr->P;
   ItemRange ir = xcd_items(w.ctr->ntile);
   uint32_t cur = 0xFFFFFFFFu, logm = 0, nch = 0;
   bool eq = false;
   const K *gSpl = nullptr;
-  for (uint32_t c = tid; c < CH; c += SCK_THREADS) sCnt[c] = 0;
+  if (PRIV) {
+    for (uint32_t c = tid; c < 2 * SCK_PCH; c += SCK_THREADS) sCnt2[c] = 0;
+  } else {
+    for (uint32_t c = tid; c < CH; c += SCK_THREADS) sCnt[c] = 0;
+  }
   if (ir.first >= ir.end) return;
   // The keys of the first chunk of a tile are loaded while the previous
   // tile's last chunk is processed, so no tile starts on an empty pipeline.
@@ -1211,33 +1226,60 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
       for (int k = 0; k < KPT; ++k) {
         const uint32_t p = cb + sck_pos<K, KPT>(k);
         const uint32_t c = p < hi ? (uint32_t)sI2C[xcs[k]] : 0u;
-        const uint32_t slot = wave_slot_add(sCnt, c, p < hi);
+        const uint32_t slot = wave_slot_add(PRIV ? sCnt2 + par * SCK_PCH : sCnt, c, p < hi);
         xcs[k] = (c << 16) | slot;
       }
       __syncthreads();
-      block_exscan_to<SCK_THREADS>(sCnt, sL, nch, sTmp);
+      const uint32_t *ccnt = PRIV ? sCnt2 + par * SCK_PCH : sCnt;  // this chunk's counts
+      const uint16_t *off16 = myRow;  // PRIV: this wavefront's offsets
+      if (PRIV) {
+        // the whole exclusive scan of the counts in every wavefront: lane
+        // l takes children [12 l, 12 l + 12) (counts past nch are zero)
+        const uint32_t lane = tid & 63u;
+        const uint4 *c4 = (const uint4 *)(ccnt + 12 * lane);
+        const uint4 a0 = c4[0], a1 = c4[1], a2 = c4[2];
+        const uint32_t v[12] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, a2.x, a2.y, a2.z, a2.w};
+        uint32_t tot = 0;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) tot += v[j];
+        uint32_t run = wave_incl_scan(tot) - tot;
+        uint64_t o[3] = {0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+          o[j / 4] |= (uint64_t)(run & 0xFFFFu) << (16 * (j % 4));
+          run += v[j];
+        }
+        uint64_t *r8 = (uint64_t *)(myRow + 12 * lane);
+        r8[0] = o[0];
+        r8[1] = o[1];
+        r8[2] = o[2];
+      } else {
+        block_exscan_to<SCK_THREADS>(sCnt, sL, nch, sTmp);
+      }
       // per child: the output address of chunk slot 0 (low bit: decode the
       // key on the way out; 0: the child would overrun its subproblem and
       // its keys are dropped, flagged as an overflow); then advance sBase
       for (uint32_t c = tid; c < nch; c += SCK_THREADS) {
         const uint32_t cd = sCd[c];
+        const uint32_t nc = ccnt[c];
+        const uint32_t lc = PRIV ? (uint32_t)off16[c] : sL[c];
         uint64_t d = 0;
-        if ((uint64_t)sBase[c] + sCnt[c] <= s.size) {
+        if ((uint64_t)sBase[c] + nc <= s.size) {
           const K *base = kptr<K>(w, R, cd & 15u) + s.off + sBase[c];
-          d = ((uint64_t)(uintptr_t)base - (uint64_t)sL[c] * sizeof(K)) | (uint64_t)(cd >> 4);
+          d = ((uint64_t)(uintptr_t)base - (uint64_t)lc * sizeof(K)) | (uint64_t)(cd >> 4);
         } else {
           atomicOr(&w.ctr->overflow, 16u);
         }
         sDst[c] = d;
-        sBase[c] += sCnt[c];
-        sCnt[c] = 0;  // its last use in this chunk: ready for the next one
+        sBase[c] += nc;
+        if (!PRIV) sCnt[c] = 0;  // its last use in this chunk: ready for the next one
       }
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
         const uint32_t p = cb + sck_pos<K, KPT>(k);
         if (p < hi) {
           const uint32_t c = xcs[k] >> 16;
-          const uint32_t q = sL[c] + (xcs[k] & 0xFFFFu);
+          const uint32_t q = (PRIV ? (uint32_t)off16[c] : sL[c]) + (xcs[k] & 0xFFFFu);
           stK[q] = xa[k];
           stC[q] = (uint16_t)c;
         }
@@ -1265,6 +1307,12 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
       // no barrier here: every wavefront finishes this write-out before it
       // reaches the next chunk's first barrier, and the staging area is
       // only written after that barrier
+      if (PRIV) {
+        // this bank was last read before the barrier above; it is counted
+        // into again two chunks on, after two more barriers
+        for (uint32_t c = tid; c < nch; c += SCK_THREADS) sCnt2[par * SCK_PCH + c] = 0;
+        par ^= 1u;
+      }
 #pragma unroll
       for (int k = 0; k < KPT; ++k) xa[k] = xb[k];
     }
@@ -2724,14 +2772,24 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
         return (size_t)ls.mmax * sizeof(K) + chk * sizeof(K) + (size_t)ls.CH * 8 + chk * 2 +
                (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + SCK_THREADS / 64 * 4 + ls.CH + 64;
       };
+      // with at most SCK_PCH children: per-wavefront scans and two counter
+      // banks in place of the block scan's offsets and counters
+      const size_t ldsPriv = lds_keys(8) - (size_t)ls.CH * 8 + (size_t)2 * SCK_PCH * 4 +
+                             (size_t)(SCK_THREADS / 64) * SCK_PCH * 2;
       TraceScope ts("scatter", l, s);
-      if (lds_keys(8) <= 163840) {
-        allow_lds(k_scatter_keys<KT, 8>, lds_keys(8));
-        hipLaunchKernelGGL((k_scatter_keys<KT, 8>), dim3(grid_for(ls.tiles, 512)),
+      // (the counter banks are read 16 bytes at a time: the tree area before
+      // them must keep that alignment)
+      if (ls.CH <= SCK_PCH && ldsPriv <= 163840 && (ls.mmax * sizeof(K)) % 16 == 0) {
+        allow_lds(k_scatter_keys<KT, 8, true>, ldsPriv);
+        hipLaunchKernelGGL((k_scatter_keys<KT, 8, true>), dim3(grid_for(ls.tiles, 512)),
+                           dim3(SCK_THREADS), ldsPriv, s, w, lv);
+      } else if (lds_keys(8) <= 163840) {
+        allow_lds(k_scatter_keys<KT, 8, false>, lds_keys(8));
+        hipLaunchKernelGGL((k_scatter_keys<KT, 8, false>), dim3(grid_for(ls.tiles, 512)),
                            dim3(SCK_THREADS), lds_keys(8), s, w, lv);
       } else {
-        allow_lds(k_scatter_keys<KT, 4>, lds_keys(4));
-        hipLaunchKernelGGL((k_scatter_keys<KT, 4>), dim3(grid_for(ls.tiles, 512)),
+        allow_lds(k_scatter_keys<KT, 4, false>, lds_keys(4));
+        hipLaunchKernelGGL((k_scatter_keys<KT, 4, false>), dim3(grid_for(ls.tiles, 512)),
                            dim3(SCK_THREADS), lds_keys(4), s, w, lv);
       }
     }
