@@ -73,14 +73,19 @@ def test_batch_in_place_and_device_offsets(api):
         assert np.array_equal(out[a:b], want)
 
 
-@pytest.mark.parametrize("levels,k,b", [(3, 4, 2), (2, 16, 4), (1, 1024, 2), (3, 64, 1)])
-def test_forced_level_plans(api, levels, k, b):
+# Keys-only scatter paths: per-wavefront scans (at most 768 children, tree
+# area a multiple of 16 bytes), the block scan for wider levels (k = 1024),
+# the block scan for a uint32 tree of two splitter slots (k * b = 2, an
+# 8-byte tree area), and per-wavefront scans for one of four.
+@pytest.mark.parametrize("kt,levels,k,b", [(U64, 3, 4, 2), (U64, 2, 16, 4), (U64, 1, 1024, 2),
+                                           (U64, 3, 64, 1), (U32, 4, 2, 1), (U32, 3, 4, 1)])
+def test_forced_level_plans(api, kt, levels, k, b):
     n = 300000
-    keys = gen(U64, n, "uniform", 50 + levels * k)
+    keys = gen(kt, n, "uniform", 50 + levels * k)
     p = api.make_params(levels=levels, k=k, overpartition_b=b, samples_per_bucket=4)
-    log("levels=%d k=%d b=%d" % (levels, k, b))
+    log("kt=%d levels=%d k=%d b=%d" % (kt, levels, k, b))
     out = to_host(api.sort_keys(to_dev(keys), params=p))
-    want, _ = oracle.oracle_sort(U64, keys)
+    want, _ = oracle.oracle_sort(kt, keys)
     assert np.array_equal(out, want)
 
 
