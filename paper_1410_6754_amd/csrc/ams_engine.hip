@@ -913,7 +913,9 @@ __global__ void __launch_bounds__(256) k_tile_scan(Ws w, Lev lv) {
 // A tile is processed in chunks of 256*KPT keys: every wavefront takes a
 // contiguous quarter of the chunk, ranks its keys among equal children with
 // ballots (input order kept), the chunk is regrouped by child in LDS and
-// written out in runs.
+// written out in runs.  Pairs use it for levels too wide for
+// k_scatter_pairs; keys-only sorts use it when a stable partition is asked
+// for.
 // ---------------------------------------------------------------------------
 template <int KT, bool PAY, int KPT>
 __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
