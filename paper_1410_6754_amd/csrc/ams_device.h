@@ -106,6 +106,12 @@ AMS_DEV uint32_t draw_pos(uint64_t state, uint32_t i, uint32_t n) {
 // an LDS result would also wait for every flat access in flight.
 template <typename T> using GMem = __attribute__((address_space(1))) T;
 
+// A 64-bit word that may alias narrower data: rows of 16-bit LDS entries are
+// written or cleared four entries at a time through it and read back entry
+// by entry, which type-based alias analysis would otherwise let the compiler
+// reorder.
+typedef uint64_t __attribute__((__may_alias__)) u64_alias;
+
 typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 

@@ -1251,7 +1251,7 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
           o[j / 4] |= (uint64_t)(run & 0xFFFFu) << (16 * (j % 4));
           run += v[j];
         }
-        uint64_t *r8 = (uint64_t *)(myRow + 12 * lane);
+        u64_alias *r8 = (u64_alias *)(myRow + 12 * lane);
         r8[0] = o[0];
         r8[1] = o[1];
         r8[2] = o[2];
@@ -1468,7 +1468,7 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_pairs(Ws w, Lev lv) 
       }
       // this wavefront's row is not read again in this chunk: clear it for
       // the next one (CHP is a multiple of 4, rows are 8-byte aligned)
-      for (uint32_t j = lane; j < CHP / 4; j += 64) ((uint64_t *)row)[j] = 0;
+      for (uint32_t j = lane; j < CHP / 4; j += 64) ((u64_alias *)row)[j] = 0;
       __syncthreads();
       // write out: consecutive slots of a child go to consecutive indices
       const uint32_t cnt = hi - cb < CHK ? hi - cb : CHK;
