@@ -2514,7 +2514,10 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     LevelShape &ls = pl.lev[l];
     ls.rmax = r;
     ls.b = b;
-    ls.a = (p && p->samples_per_bucket) ? p->samples_per_bucket : (l == 0 ? 8 : 4);
+    // samples per bucket: 8 for the split of the whole input; 2 below,
+    // where a subproblem's sample costs more than its slightly less even
+    // buckets (the grouping absorbs them)
+    ls.a = (p && p->samples_per_bucket) ? p->samples_per_bucket : (l == 0 ? 8 : 2);
     ls.mmax = std::min<uint32_t>(2048, r * b);
     ls.Smax = (uint32_t)std::min<uint64_t>(Scap, align256((uint64_t)ls.a * ls.mmax));
     if (ls.Smax < 256) ls.Smax = 256;
