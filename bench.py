@@ -257,13 +257,15 @@ def main() -> int:
     # every HBM pass against the peak: the partition passes (count reads the
     # keys, scatter reads and writes them) and the base case (reads and
     # writes them once); algorithmic bytes per launch over its average time
+    ceiling = copy_ceiling()
     passes = {}
     for k in ("count", "scatter", "finish"):
         if k in per:
             am = per[k]["total_ms"] / per[k]["launches"]
             gbs = alg_bytes[k] / (am * 1e-3) / 1e9
             passes[k] = {"avg_launch_ms": round(am, 4), "algorithmic_bytes_per_launch": alg_bytes[k],
-                         "GB_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+                         "GB_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                         "frac_of_copy": round(gbs / ceiling["GB_per_s"], 4)}
     if "count" in passes and "scatter" in passes:
         # one partition level as a whole: count reads the keys, scatter reads
         # and writes them (3w bytes per key moved by the implementation, of
@@ -273,7 +275,8 @@ def main() -> int:
         passes["partition_level"] = {
             "ms": round(lm, 4), "implementation_bytes": ib,
             "GB_per_s": round(ib / (lm * 1e-3) / 1e9, 1),
-            "frac_of_peak": round(ib / (lm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "frac_of_peak": round(ib / (lm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "frac_of_copy": round(ib / (lm * 1e-3) / 1e9 / ceiling["GB_per_s"], 4)}
     if args.trace_file:
         with open(args.trace_file, "w") as f:
             json.dump({"workload": args.workload, "trace": trace, "kernels": kernels}, f, indent=1)
@@ -306,12 +309,39 @@ def main() -> int:
                    "payload": "uint32" if pay else None, "params": pkw},
         "roofline": roof,
         "passes": passes,
+        "copy_ceiling": ceiling,
         "cpu_baseline": cpu,
         "kernels": kernels,
         "verified_sorted": verified,
     }
     print(json.dumps(line))
     return 0
+
+
+def copy_ceiling():
+    """The practical HBM ceiling: a plain 2 GiB device-to-device copy (torch's
+    copy kernel, 4 GiB moved) timed with events, best of five."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.int64, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    moved = 2 * src.numel() * src.element_size()
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = moved / (best * 1e-3) / 1e9
+    return {"kernel": "device-to-device copy of 2 GiB", "bytes_moved": moved, "ms": round(best, 4),
+            "GB_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def _log(msg):
