@@ -60,9 +60,11 @@ typedef int ams_status;
 /* Tuning parameters.  A zero field means "choose automatically": the
  * autotuner's choice for the call's shape class when ams_autotune has made
  * one, else the built-in defaults (k = 256, b = 4 for one sort; k = 128,
- * b = 2 for a batch of several segments; a = 8 samples per bucket at the
- * first level and 2 below; cutoff 32; tiles of 64 Ki keys from 2^27 keys,
- * else 32 Ki); passing NULL means all defaults.  Names follow the
+ * b = 2 for a batch of several segments, and b = 2 below the first level
+ * when the planned leaves average at most 30% of the base case's capacity;
+ * a = 8 samples per bucket at the first level and 2 below; cutoff 32; tiles
+ * of 64 Ki keys from 2^27 keys, else 32 Ki); passing NULL means all
+ * defaults.  Names follow the
  * paper: k is the number of groups per level (the paper's r), b the
  * overpartitioning factor, a the oversampling factor (Section 6). */
 typedef struct {

@@ -2508,17 +2508,23 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     }
   }
   pl.L = L;
+  // below the first level, b = 2 when the leaves will be small (on average
+  // at most 30% of the base case's capacity): half the buckets cost less in
+  // every pass, and the less even groups still fit a leaf
+  double capL = 1.0;
+  for (uint32_t l = 0; l < L; ++l) capL *= r;
+  const bool smallLeaves = (double)mx / capL <= 0.3 * C;
   uint64_t P = pl.nbig, keys = keysBig;
   uint64_t leaves = nroots + 64;
   for (uint32_t l = 0; l < L; ++l) {
     LevelShape &ls = pl.lev[l];
     ls.rmax = r;
-    ls.b = b;
+    ls.b = (l > 0 && smallLeaves && !(p && p->overpartition_b)) ? std::min<uint32_t>(b, 2) : b;
     // samples per bucket: 8 for the split of the whole input; 2 below,
     // where a subproblem's sample costs more than its slightly less even
     // buckets (the grouping absorbs them)
     ls.a = (p && p->samples_per_bucket) ? p->samples_per_bucket : (l == 0 ? 8 : 2);
-    ls.mmax = std::min<uint32_t>(2048, r * b);
+    ls.mmax = std::min<uint32_t>(2048, r * ls.b);
     ls.Smax = (uint32_t)std::min<uint64_t>(Scap, align256((uint64_t)ls.a * ls.mmax));
     if (ls.Smax < 256) ls.Smax = 256;
     ls.TC = TC;
