@@ -198,18 +198,18 @@ extern "C" ams_status ams_autotune(ams_key_t t, const void *d_kin, const uint32_
     return AMS_OK;
   };
 
-  // start from the built-in defaults, then improve one parameter at a time
+  // start from the built-in defaults, then improve one parameter at a time;
+  // b stays 0 (the plan's own choice per level) until a value is tried
   ams_params cur;
   memset(&cur, 0, sizeof cur);
-  cur.k = 256;
-  cur.overpartition_b = 4;
   cur.base_cutoff = 32;
   double cur_ms = 0;
   if ((st = evaluate(cur, cur_ms))) return st;
-  {  // the levels and tile size the plan picked by itself
+  {  // the levels, group count and tile size the plan picked by itself
     Plan pl;
     if (make_plan(pl, (int)t, pay, sizes.data(), (uint32_t)num, 0, &cur) == AMS_OK) {
       cur.levels = pl.L;
+      cur.k = pl.L ? pl.lev[0].rmax : 256;
       cur.tile_keys = pl.L ? pl.lev[0].TC : 32768;
     }
   }
@@ -219,8 +219,8 @@ extern "C" ams_status ams_autotune(ams_key_t t, const void *d_kin, const uint32_
     std::vector<uint32_t> values;
   };
   const std::vector<Dim> dims = {
-      {&ams_params::k, {128, 512, 1024}},
-      {&ams_params::overpartition_b, {2, 8}},
+      {&ams_params::k, {128, 256, 512, 1024}},
+      {&ams_params::overpartition_b, {2, 4, 8}},
       {&ams_params::base_cutoff, {16, 24, 48}},
       {&ams_params::tile_keys, {16384, 32768, 65536}},
       {&ams_params::levels, {Lauto + 1, Lauto > 1 ? Lauto - 1 : Lauto + 2}},
