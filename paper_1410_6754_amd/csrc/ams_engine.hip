@@ -422,6 +422,14 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
       }
       if (ballot(same) == lanes && ntv == 256u * CU) {
         if (tid % 64 == 0) atomicAdd(&sH[c0], 64u * CU);
+      } else if (__popcll(ballot(ids[0] == __builtin_amdgcn_readfirstlane(ids[0]))) >= 32) {
+        // clustered input (sorted runs): most lanes of a row share a bucket,
+        // so each row adds once per bucket instead of once per key
+#pragma unroll
+        for (uint32_t u = 0; u < CU; ++u) {
+          const uint32_t p = base + (u / V) * (V * 256u) + V * tid + (u % V);
+          wave_count_add(sH, ids[u], p < hi);
+        }
       } else {
 #pragma unroll
         for (uint32_t u = 0; u < CU; ++u) {
