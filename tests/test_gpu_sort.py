@@ -127,6 +127,17 @@ def test_two_levels(api):
     check_sort_keys(api, U64, gen(U64, n, "uniform", 11), what="2lvl")
 
 
+# Sorted and reversed input over two levels: at the second level a bucket
+# holds a few thousand keys, so the count kernel's rows mostly share a
+# bucket (row-wise adds) while the tile tails stay partial.
+@pytest.mark.parametrize("kt", [U64, U32])
+@pytest.mark.parametrize("dist", ["sorted", "reversed"])
+def test_two_levels_ordered_input(api, kt, dist):
+    n = (1 << 22) + 12345
+    log("two levels kt=%d %s n=%d" % (kt, dist, n))
+    check_sort_keys(api, kt, gen(kt, n, dist, 13), what="2lvl " + dist)
+
+
 def test_in_place(api):
     keys = gen(U64, 100000, "uniform", 12)
     import oracle
