@@ -12,7 +12,11 @@ started at state s is therefore mix64(s + i * gamma), a pure function of
 (s, i).
 
 Pin: ``tests/golden/splitmix64.txt`` holds the generator's published first
-outputs for seeds 0 and 1234567.
+outputs for seeds 0 and 1234567.  ``stream_state`` is a convention of this
+project (the paper fixes no generator); its first fold is the published
+first output at the seed, distinct (level, root, offset) keys give distinct
+states, and ``sample_positions`` for n = 2^k is the top k bits of the
+published stream, uniform by a chi-square test.
 """
 
 from __future__ import annotations

@@ -77,7 +77,12 @@ def select_splitters(sorted_sample, a: int, m: int) -> np.ndarray:
 def eq_enabled(splitters) -> bool:
     """Equality buckets are switched on for a subproblem when two splitters
     are equal (reading of Appendix D, which adds one comparison per element
-    to separate keys equal to a splitter)."""
+    to separate keys equal to a splitter).
+
+    Splitters are sorted, so two equal ones are neighbours.  Pin: brute force
+    over every sorted array of up to 6 splitters from a 4-letter alphabet
+    ("some two splitters are equal"), which also catches planted mistakes.
+    """
     s = np.asarray(splitters, dtype=np.uint64)
     return bool(s.size > 1 and np.any(s[1:] == s[:-1]))
 
@@ -216,6 +221,12 @@ def children(counts, eq_on: bool, r: int):
     is then cut at its FINAL ids.  Every maximal run of non-FINAL ids with
     keys becomes a REG child, every FINAL id a FINAL child.  Empty pieces are
     dropped.  Returns a list of (first_id, end_id, size, kind).
+
+    Pin: the hand-worked cases of ``tests/golden/children.txt`` (threshold
+    met exactly, a final id inside a group, empty pieces after a final id,
+    a large regular bucket, equality buckets off, all keys equal), which
+    fail for each planted mistake (``>`` for ``>=``, no cut at a final id,
+    empty pieces kept, a final id on a regular bucket).
     """
     c = [int(v) for v in counts]
     N = sum(c)

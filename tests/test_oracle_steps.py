@@ -239,3 +239,165 @@ def test_pins_catch_planted_oracle_mistakes():
     keys = np.array([10, 15, 20, 31], dtype=np.uint64)
     wrong_side = np.searchsorted(s, keys, side="right")  # x <= s counted as above
     assert not np.array_equal(steps.classify(keys, s, False), wrong_side)
+
+
+# ----------------------------------------------------------------------------
+# children(): hand-worked golden cases and planted mistakes
+# ----------------------------------------------------------------------------
+
+def _golden_children():
+    cases = []
+    with open(os.path.join(GOLDEN, "children.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            head, counts, kids = [p.strip() for p in line.split("|")]
+            r, eq_on = [int(v) for v in head.split()]
+            counts = [int(v) for v in counts.split()]
+            want = []
+            for k in kids.split(";"):
+                a, b, size, kind = k.split()
+                want.append((int(a), int(b), int(size), steps.FINAL if kind == "F" else steps.REG))
+            cases.append((r, bool(eq_on), counts, want))
+    return cases
+
+
+def test_children_golden_cases():
+    cases = _golden_children()
+    assert len(cases) >= 8
+    for r, eq_on, counts, want in cases:
+        assert steps.children(counts, eq_on, r) == want, (r, eq_on, counts)
+    assert steps.children([0, 0, 0], True, 2) == []
+
+
+def _children_variant(counts, eq_on, r, *, strict=False, cut=True, drop_empty=True,
+                      even_final=False):
+    """children() with one planted mistake switched on."""
+    c = [int(v) for v in counts]
+    N = sum(c)
+    if N == 0:
+        return []
+    tfin = -(-N // r)
+    def is_final(i):
+        if not eq_on or (i % 2 == 0 and not even_final):
+            return False
+        return c[i] > tfin if strict else c[i] >= tfin
+    final = [is_final(i) for i in range(len(c))]
+    w = [0 if final[i] else c[i] for i in range(len(c))]
+    _, starts = steps.pack(w, r)
+    ends = starts[1:] + [len(c)]
+    out = []
+    for gs, ge in zip(starts, ends):
+        run_start = gs
+        for i in range(gs, ge):
+            if final[i] and cut:
+                size = sum(c[run_start:i])
+                if size or not drop_empty:
+                    out.append((run_start, i, size, steps.REG))
+                out.append((i, i + 1, c[i], steps.FINAL))
+                run_start = i + 1
+        size = sum(c[run_start:ge])
+        if size or not drop_empty:
+            out.append((run_start, ge, size, steps.REG))
+    return out
+
+
+def test_children_pins_catch_planted_mistakes():
+    cases = _golden_children()
+    # the variant with no mistake switched on reproduces every golden case
+    for r, eq_on, counts, want in cases:
+        assert _children_variant(counts, eq_on, r) == want
+    mistakes = {
+        "final threshold > instead of >=": dict(strict=True),
+        "no cut at a final id": dict(cut=False),
+        "empty piece kept": dict(drop_empty=False),
+        "final id on a regular (even) bucket": dict(even_final=True),
+    }
+    for name, kw in mistakes.items():
+        caught = any(_children_variant(counts, eq_on, r, **kw) != want
+                     for r, eq_on, counts, want in cases)
+        assert caught, name
+
+
+# ----------------------------------------------------------------------------
+# eq_enabled(): brute force over small sorted splitter arrays
+# ----------------------------------------------------------------------------
+
+def _eq_brute(spl):
+    """Some two splitters (any positions) are equal."""
+    s = [int(v) for v in spl]
+    return any(s[i] == s[j] for i in range(len(s)) for j in range(i + 1, len(s)))
+
+
+def test_eq_enabled_brute_force():
+    seen = 0
+    for n in range(0, 7):
+        for seq in itertools.combinations_with_replacement(range(4), n):
+            spl = np.array(seq, dtype=np.uint64)  # sorted, as splitters are
+            assert steps.eq_enabled(spl) == _eq_brute(seq), seq
+            seen += 1
+    assert seen > 200
+    # large ord values (top bit set) compare as unsigned
+    big = np.array([1 << 63, (1 << 63) + 1, (1 << 64) - 1], dtype=np.uint64)
+    assert not steps.eq_enabled(big)
+    assert steps.eq_enabled(np.array([5, (1 << 64) - 1, (1 << 64) - 1], dtype=np.uint64))
+
+
+def test_eq_enabled_pins_catch_planted_mistakes():
+    def skip_one(spl):  # compares s[i] with s[i+2]
+        s = np.asarray(spl, dtype=np.uint64)
+        return bool(s.size > 2 and np.any(s[2:] == s[:-2]))
+
+    def first_pair_only(spl):  # looks at the first two splitters only
+        s = np.asarray(spl, dtype=np.uint64)
+        return bool(s.size > 1 and s[0] == s[1])
+
+    def wrong_size_guard(spl):  # needs three splitters before it looks
+        s = np.asarray(spl, dtype=np.uint64)
+        return bool(s.size > 2 and np.any(s[1:] == s[:-1]))
+
+    for bad in (skip_one, first_pair_only, wrong_size_guard):
+        caught = False
+        for n in range(0, 7):
+            for seq in itertools.combinations_with_replacement(range(4), n):
+                if bad(np.array(seq, dtype=np.uint64)) != _eq_brute(seq):
+                    caught = True
+        assert caught, bad.__name__
+
+
+# ----------------------------------------------------------------------------
+# sample positions: tied to the published SplitMix64 outputs
+# ----------------------------------------------------------------------------
+
+def test_stream_state_first_stage_is_published_output():
+    # the first fold is SplitMix64's first output at the seed, which the
+    # golden file pins (seed 0 -> 16294208416658607535)
+    assert orng.mix64(orng.GAMMA) == 16294208416658607535
+    assert orng.splitmix64_outputs(1234567, 1)[0] == orng.mix64(1234567 + orng.GAMMA)
+
+
+def test_sample_positions_are_top_bits_of_the_stream():
+    # for n = 2^k, floor(n u / 2^64) is the top k bits of u, and u_i is output
+    # i+1 of SplitMix64 started at the subproblem's stream state
+    for k in (1, 7, 20, 32):
+        st = orng.stream_state(3, 1, 4, 1000)
+        outs = orng.splitmix64_outputs(st, 64)
+        pos = orng.sample_positions(3, 1, 4, 1000, 1 << k, 64)
+        assert pos == [o >> (64 - k) for o in outs]
+
+
+def test_sample_positions_uniform_chi_square():
+    # 65536 draws over 256 cells: chi-square with 255 degrees of freedom
+    # stays below 340 with probability > 0.999
+    pos = np.asarray(orng.sample_positions(14106754, 0, 0, 0, 256 * 1000, 65536)) // 1000
+    cnt = np.bincount(pos, minlength=256)
+    e = 65536 / 256
+    chi2 = float(((cnt - e) ** 2 / e).sum())
+    assert chi2 < 340, chi2
+
+
+def test_stream_states_are_distinct():
+    # every (level, root, offset) key gives its own stream
+    states = {orng.stream_state(7, lv, root, off)
+              for lv in range(4) for root in range(16) for off in (0, 1, 4096, 1 << 20)}
+    assert len(states) == 4 * 16 * 4
