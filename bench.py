@@ -38,7 +38,8 @@ WORKLOADS = {
     "reversed_u64_2^28": (1 << 28, W.KEY_U64, "reversed", False,
                           dict(levels=2, k=256, overpartition_b=4), 2),
     "uniform_u64_2^20": (1 << 20, W.KEY_U64, "uniform", False,
-                         dict(levels=1, k=256, overpartition_b=1, samples_per_bucket=16), 1),
+                         dict(levels=1, k=256, overpartition_b=1, samples_per_bucket=16,
+                              base_cutoff=1024), 1),
     "pairs_few_2^27": (1 << 27, W.KEY_U64, "few", True, dict(), 3),
     "pairs_zipf_2^27": (1 << 27, W.KEY_U64, "zipf", True, dict(), 3),
     "pairs_equal_2^27": (1 << 27, W.KEY_U64, "equal", True, dict(), 3),

@@ -56,6 +56,25 @@ typedef int ams_status;
 #define AMS_EAGAIN (-4)       /* server: pending queue full, try again */
 #define AMS_EUNSUPPORTED (-5) /* size or option outside what the library supports */
 #define AMS_ENOTFOUND (-6)    /* server: unknown or released ticket */
+#define AMS_EDEVICE (-7)      /* the device raised an error (AMS_DEVERR_* bits): a table
+                                 bound was exceeded and the output is not valid */
+
+/* Largest segment (keys of one sort, of one batch segment or of one served
+ * request): 2^32 - 2^20.  Payloads are 32-bit positions, and the kernels'
+ * 32-bit tile arithmetic stays exact up to this size. */
+#define AMS_MAX_SEGMENT ((1ull << 32) - (1ull << 20))
+
+/* Device error bits.  Every table the kernels fill is sized on the host to an
+ * upper bound of what the plan can produce; a kernel that would exceed one
+ * (which means a bug, or the test hook AMS_FLAG_TEST_TINY_TABLES) skips the
+ * write, keeps every access in bounds and raises one of these bits in the
+ * run's counters and in the device's error word (ams_device_errors). */
+#define AMS_DEVERR_TABLE 1u   /* the leaf list or an active-subproblem list was full */
+#define AMS_DEVERR_ACTIVE 2u  /* more active subproblems than the level's table */
+#define AMS_DEVERR_TILES 4u   /* more tiles, tile blocks or sample blocks than planned */
+#define AMS_DEVERR_GROUPS 8u  /* a grouping gave more children than its table holds */
+#define AMS_DEVERR_RANGE 16u  /* a scatter destination fell outside its child's range */
+#define AMS_DEVERR_LEAF 32u   /* a leaf reached outside its segment */
 
 /* Tuning parameters.  A zero field means "choose automatically": the
  * autotuner's choice for the call's shape class when ams_autotune has made
@@ -72,7 +91,8 @@ typedef struct {
   uint32_t k;                  /* groups per level r; power of two, 2..1024 */
   uint32_t overpartition_b;    /* buckets per group b; power of two, k*b <= 2048 */
   uint32_t samples_per_bucket; /* oversampling factor a */
-  uint32_t tile_keys;          /* keys per workgroup tile in a level pass (multiple of 4096) */
+  uint32_t tile_keys;          /* keys per workgroup tile in a level pass (multiple of 4096,
+                                  at most 2^19) */
   uint32_t base_cutoff;        /* largest bucket handed to the all-pairs ranker, <= 1024 */
   uint64_t seed;               /* sampling seed (0 = fixed default) */
   uint32_t flags;              /* AMS_FLAG_* */
@@ -88,6 +108,11 @@ typedef struct {
 #define AMS_FLAG_SAMPLED_LEAF_SPLIT 4u /* base case: split every leaf by sampled splitters
                                           instead of first trying its key range; the sorted
                                           output is the same either way (test hook) */
+#define AMS_FLAG_CHECK 8u /* the call waits for its stream before returning and returns
+                             AMS_EDEVICE if its kernels raised a device error */
+#define AMS_FLAG_TEST_TINY_TABLES 16u /* test hook: the leaf list holds one entry, so any
+                                         sort with more than one leaf raises
+                                         AMS_DEVERR_TABLE (its output is then invalid) */
 
 /* Bytes of device workspace a call with these arguments needs.  Returns 0 on
  * invalid arguments.  ams_sort_* accept d_ws = NULL, in which case they
@@ -100,8 +125,8 @@ size_t ams_batch_workspace_bytes(ams_key_t t, const uint64_t *h_offsets, size_t 
                                  int with_vals, const ams_params *p);
 
 /* Sort n keys.  d_in (n keys) and d_out (n keys) may be the same buffer
- * (in-place).  n must be below 2^32.  Section 6 (AMS-sort), Section 1
- * (output requirement). */
+ * (in-place).  n <= AMS_MAX_SEGMENT, else AMS_EUNSUPPORTED.  Section 6
+ * (AMS-sort), Section 1 (output requirement). */
 ams_status ams_sort_keys(ams_key_t t, const void *d_in, void *d_out, size_t n, void *d_ws,
                          size_t ws_bytes, void *stream, const ams_params *p);
 
@@ -149,6 +174,39 @@ void ams_autotune_clear(void);
 
 /* Message for the calling thread's most recent error ("" if none). */
 const char *ams_last_error(void);
+
+/* Device errors.  Sort calls return once their kernels are enqueued, so an
+ * error a kernel raises later cannot be their return value (unless the call
+ * passed AMS_FLAG_CHECK).  Every such error is also ORed into a per-device
+ * error word; this call waits for `stream` (a stream of the current device),
+ * stores the word's AMS_DEVERR_* bits in *bits (0 = no error since the last
+ * clear) and, when `clear` is nonzero, resets it. */
+ams_status ams_device_errors(void *stream, uint32_t *bits, int clear);
+
+/* Statistics of the last sort that ran in a caller-provided workspace d_ws
+ * (its counters sit at the start of the workspace).  Waits for `stream`.
+ * Level l's subproblems are what its partition pass read and wrote; keys
+ * placed in final children (equality buckets, Appendix D) drop out of later
+ * passes.  The imbalance of a subproblem is its grouping's maximum load L*
+ * over the average ceil(W / r) of the W keys outside final children, the
+ * ratio that the load-balance lemma of Section 6 bounds by 1 + eps. */
+typedef struct {
+  uint32_t device_errors;     /* AMS_DEVERR_* bits raised by the run */
+  uint32_t levels;            /* partition levels of the plan */
+  uint32_t subproblems[4];    /* subproblems level l partitioned */
+  uint64_t keys[4];           /* keys in them */
+  uint64_t final_keys[4];     /* keys level l placed in final children */
+  uint32_t max_child[4];      /* largest regular child level l produced */
+  uint32_t tiles[4];          /* tiles (workgroup items) of level l's passes */
+  double imbalance_max[4];    /* largest L* / ceil(W / r) over level l's subproblems */
+  double imbalance_mean[4];   /* its mean over the subproblems with W > 0 */
+  uint32_t leaves;            /* leaves the base-case kernel processed */
+  uint32_t big_leaves;        /* of those, larger than one workgroup's LDS (merged) */
+  uint64_t leaf_keys;         /* keys sorted in LDS by the base case */
+  uint64_t copy_keys;         /* keys of final children copied to the output */
+  uint64_t big_keys;          /* keys in oversized leaves */
+} ams_run_stats;
+ams_status ams_workspace_stats(const void *d_ws, void *stream, ams_run_stats *out);
 
 /* Per-kernel timing (tracing).  ams_trace_start() makes every later sort
  * call of the calling thread bracket each kernel launch with a pair of
@@ -204,8 +262,12 @@ ams_server *ams_server_create(int device, size_t hbm_budget, uint32_t max_pendin
                               uint32_t n_streams, ams_status *st);
 
 /* Queue a request.  d_keys must stay valid until the request completes.
- * Returns AMS_ENOMEM if the request alone can never fit the budget and
- * AMS_EAGAIN if max_pending requests are already queued or running. */
+ * Returns AMS_ENOMEM if the request alone can never fit the budget,
+ * AMS_EAGAIN if max_pending requests are already queued or running and
+ * AMS_EUNSUPPORTED for n > AMS_MAX_SEGMENT.  A request whose batch fails
+ * (an allocation, a launch, or a device error its kernels raise) finishes
+ * with that status in its ams_req_stats and from ams_wait; the server goes
+ * on serving later requests. */
 ams_status ams_submit(ams_server *srv, ams_key_t t, const void *d_keys, const uint32_t *d_vals,
                       size_t n, uint64_t *ticket);
 
@@ -232,6 +294,11 @@ ams_status ams_release(ams_server *srv, uint64_t ticket);
 
 /* Drain outstanding work, free everything. */
 void ams_server_destroy(ams_server *srv);
+
+/* Test hook for failure handling: the next `count` batches the server forms
+ * fail as if their device allocation had failed, so their requests finish
+ * with AMS_ENOMEM. */
+ams_status ams_server_inject_alloc_failures(ams_server *srv, uint32_t count);
 
 /* ------------------------------------------------------------------------
  * Step entry points: one step of the path on one subproblem, for checking

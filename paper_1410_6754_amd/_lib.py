@@ -24,13 +24,25 @@ AMS_EHIP = -3
 AMS_EAGAIN = -4
 AMS_EUNSUPPORTED = -5
 AMS_ENOTFOUND = -6
+AMS_EDEVICE = -7
+
+AMS_MAX_SEGMENT = (1 << 32) - (1 << 20)
 
 AMS_FLAG_EQ_ALWAYS = 1
 AMS_FLAG_STABLE_PARTITION = 2
 AMS_FLAG_SAMPLED_LEAF_SPLIT = 4
+AMS_FLAG_CHECK = 8
+AMS_FLAG_TEST_TINY_TABLES = 16
+
+AMS_DEVERR_TABLE = 1
+AMS_DEVERR_ACTIVE = 2
+AMS_DEVERR_TILES = 4
+AMS_DEVERR_GROUPS = 8
+AMS_DEVERR_RANGE = 16
+AMS_DEVERR_LEAF = 32
 
 _STATUS = {0: "AMS_OK", -1: "AMS_EINVAL", -2: "AMS_ENOMEM", -3: "AMS_EHIP",
-           -4: "AMS_EAGAIN", -5: "AMS_EUNSUPPORTED", -6: "AMS_ENOTFOUND"}
+           -4: "AMS_EAGAIN", -5: "AMS_EUNSUPPORTED", -6: "AMS_ENOTFOUND", -7: "AMS_EDEVICE"}
 
 
 class AmsError(RuntimeError):
@@ -82,6 +94,33 @@ class TraceEntry(ctypes.Structure):
     ]
 
 
+class RunStats(ctypes.Structure):
+    """Mirror of ams_run_stats."""
+    _fields_ = [
+        ("device_errors", ctypes.c_uint32),
+        ("levels", ctypes.c_uint32),
+        ("subproblems", ctypes.c_uint32 * 4),
+        ("keys", ctypes.c_uint64 * 4),
+        ("final_keys", ctypes.c_uint64 * 4),
+        ("max_child", ctypes.c_uint32 * 4),
+        ("tiles", ctypes.c_uint32 * 4),
+        ("imbalance_max", ctypes.c_double * 4),
+        ("imbalance_mean", ctypes.c_double * 4),
+        ("leaves", ctypes.c_uint32),
+        ("big_leaves", ctypes.c_uint32),
+        ("leaf_keys", ctypes.c_uint64),
+        ("copy_keys", ctypes.c_uint64),
+        ("big_keys", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {}
+        for f, _ in self._fields_:
+            v = getattr(self, f)
+            d[f] = list(v) if isinstance(v, ctypes.Array) else v
+        return d
+
+
 # (name, restype, argtypes) of every exported symbol declared in include/ams.h
 _P = ctypes.c_void_p
 _U32 = ctypes.c_uint32
@@ -112,6 +151,9 @@ EXPORTS = [
     ("ams_step_base_case", _I, [_I, _P, _P, _P, _P, _SZ, _U32, _P]),
     ("ams_autotune", _I, [_I, _P, _P, _P, _SZ, _P, _U32, _P, _P]),
     ("ams_autotune_clear", None, []),
+    ("ams_device_errors", _I, [_P, _P, _I]),
+    ("ams_workspace_stats", _I, [_P, _P, _P]),
+    ("ams_server_inject_alloc_failures", _I, [_P, _U32]),
 ]
 
 _lib = None

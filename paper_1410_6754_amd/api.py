@@ -230,6 +230,7 @@ __all__ = [
     "workspace_bytes", "batch_workspace_bytes", "alloc_workspace", "sort_keys", "sort_pairs",
     "sort_batch", "step_splitters", "step_level", "step_pack", "step_base_case", "_lib",
     "trace_start", "trace_stop", "autotune", "autotune_clear", "params_dict",
+    "device_errors", "workspace_stats",
 ]
 
 
@@ -245,3 +246,20 @@ def trace_stop() -> list:
     n = lib().ams_trace_stop(arr, n)
     return [{"name": arr[i].name.decode(), "launches": arr[i].launches,
              "total_ms": arr[i].total_ms, "max_ms": arr[i].max_ms} for i in range(n)]
+
+
+def device_errors(clear: bool = True, stream=None) -> int:
+    """AMS_DEVERR_* bits raised on the current device since the last clear
+    (waits for the stream)."""
+    bits = ctypes.c_uint32(0)
+    check(lib().ams_device_errors(_stream(stream), ctypes.byref(bits), int(clear)))
+    return int(bits.value)
+
+
+def workspace_stats(workspace: torch.Tensor, stream=None) -> dict:
+    """Counters of the last sort that ran in ``workspace`` (waits for the
+    stream): per-level subproblems, keys, final keys, largest child and
+    imbalance; leaves and their keys."""
+    st = _lib.RunStats()
+    check(lib().ams_workspace_stats(workspace.data_ptr(), _stream(stream), ctypes.byref(st)))
+    return st.as_dict()

@@ -21,6 +21,9 @@ ams_status copy_splitters(const Plan &pl, void *ws, void *d_out, uint32_t m, hip
 ams_status run_sample_only(const Plan &pl, void *wsv, const RootSource &rs, hipStream_t s);
 ams_status trace_start();
 int trace_stop(ams_trace_entry *out, int max);
+ams_status device_errors(hipStream_t s, uint32_t *bits, bool clear);
+ams_status run_errors(const void *ws, hipStream_t s, uint32_t *bits);
+ams_status run_stats(const void *ws, hipStream_t s, ams_run_stats *out);
 }  // namespace ams
 
 using namespace ams;
@@ -61,6 +64,20 @@ struct WsGuard {
   }
 };
 
+// With AMS_FLAG_CHECK: wait for the run and turn a device error it raised
+// into AMS_EDEVICE.
+ams_status checked(const Plan &pl, ams_status st, const void *ws, hipStream_t s) {
+  if (st || !(pl.flags & AMS_FLAG_CHECK)) return st;
+  uint32_t bits = 0;
+  st = run_errors(ws, s, &bits);
+  if (st) return st;
+  if (bits) {
+    set_error("the device raised error bits 0x%x (a table bound was exceeded)", bits);
+    return AMS_EDEVICE;
+  }
+  return AMS_OK;
+}
+
 ams_status sort_single(ams_key_t t, const void *d_kin, const uint32_t *d_vin, void *d_kout,
                        uint32_t *d_vout, size_t n, void *d_ws, size_t ws_bytes, void *stream,
                        const ams_params *p, bool pay) {
@@ -90,7 +107,8 @@ ams_status sort_single(ams_key_t t, const void *d_kin, const uint32_t *d_vin, vo
   rs.single.vout = pay ? d_vout : nullptr;
   rs.single.n = n;
   rs.single.tmp_off = 0;
-  return run_plan_ex(pl, ws.ptr, rs, s, nullptr, nullptr, nullptr, nullptr, true);
+  st = run_plan_ex(pl, ws.ptr, rs, s, nullptr, nullptr, nullptr, nullptr, true);
+  return checked(pl, st, ws.ptr, s);
 }
 
 }  // namespace
@@ -99,7 +117,25 @@ extern "C" {
 
 const char *ams_last_error(void) { return ams::last_error(); }
 
-const char *ams_version(void) { return "ams-mi355x 0.1 (gfx950)"; }
+const char *ams_version(void) { return "ams-mi355x 0.2 (gfx950)"; }
+
+ams_status ams_device_errors(void *stream, uint32_t *bits, int clear) {
+  set_error("");
+  if (!bits) {
+    set_error("bits is NULL");
+    return AMS_EINVAL;
+  }
+  return device_errors((hipStream_t)stream, bits, clear != 0);
+}
+
+ams_status ams_workspace_stats(const void *d_ws, void *stream, ams_run_stats *out) {
+  set_error("");
+  if (!d_ws || !out) {
+    set_error("NULL workspace or output");
+    return AMS_EINVAL;
+  }
+  return run_stats(d_ws, (hipStream_t)stream, out);
+}
 
 ams_status ams_trace_start(void) { return ams::trace_start(); }
 
@@ -199,7 +235,8 @@ ams_status ams_sort_batch(ams_key_t t, const void *d_kin, const uint32_t *d_vin,
   rs.kout = (char *)d_kout;
   rs.vout = pay ? d_vout : nullptr;
   rs.d_offsets = offs;
-  return run_plan_ex(pl, ws.ptr, rs, s, nullptr, nullptr, nullptr, nullptr, true);
+  st = run_plan_ex(pl, ws.ptr, rs, s, nullptr, nullptr, nullptr, nullptr, true);
+  return checked(pl, st, ws.ptr, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,7 +337,8 @@ ams_status ams_step_level(ams_key_t t, const void *d_in, void *d_out, size_t n,
     set_error("step_level: %s", hipGetErrorString(e));
     return AMS_EHIP;
   }
-  return AMS_OK;
+  pl.flags |= AMS_FLAG_CHECK;
+  return checked(pl, AMS_OK, ws.ptr, s);
 }
 
 ams_status ams_step_pack(const uint32_t *d_w, uint32_t nb, uint32_t r, uint32_t *d_out,

@@ -21,6 +21,7 @@
 // and the leaves are finished by k_finish: in-LDS split with a small sampled
 // splitter set, then all-pairs ranking inside every small bucket.
 #include <stdarg.h>
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -38,9 +39,32 @@ struct Ctr {
   uint32_t nact[MAXLEV + 1];
   uint32_t nleaf;
   uint32_t P, ntile, nblk, nsblk;
-  uint32_t overflow;
-  uint32_t pad[5];
+  uint32_t overflow;  // AMS_DEVERR_* bits raised by this run
+  uint32_t nbig;      // oversized leaves (merge fallback)
+  uint32_t L;         // partition levels of the plan
+  // statistics of the run, per level (ams_workspace_stats)
+  uint32_t lv_sub[MAXLEV];       // subproblems partitioned
+  uint32_t lv_maxchild[MAXLEV];  // largest regular child produced
+  uint32_t lv_imb_max[MAXLEV];   // max of L* / ceil(W / r), 16.16 fixed point
+  uint32_t lv_tiles[MAXLEV];     // tiles of the level pass
+  uint32_t pad[3];
+  unsigned long long lv_keys[MAXLEV];     // keys in the partitioned subproblems
+  unsigned long long lv_final[MAXLEV];    // keys placed in final children
+  unsigned long long lv_imb_sum[MAXLEV];  // sum of the ratio over subproblems
+  unsigned long long leaf_keys[3];        // keys in leaves, by leaf kind
 };
+static_assert(sizeof(Ctr) % 8 == 0 && offsetof(Ctr, lv_keys) % 8 == 0, "Ctr layout");
+
+// Every device error any run on this device has raised since the host last
+// cleared it (ams_device_errors): sort calls on caller streams return before
+// their kernels run, so a table bound exceeded on the device is recorded
+// here as well as in the run's own counters.
+__device__ uint32_t g_dev_errors;
+
+AMS_DEV void raise_error(Ctr *c, uint32_t bits) {
+  atomicOr(&c->overflow, bits);
+  atomicOr(&g_dev_errors, bits);
+}
 
 struct Ws {
   Root *roots;
@@ -140,9 +164,36 @@ AMS_DEV uint32_t *vptr(const Ws &w, const Root &R, uint32_t buf) {
   return w.tmpV + R.tmp_off;
 }
 
-AMS_DEV void push_leaf(const Ws &w, Seg s) {
+// Leaf counts of one thread, summed per wavefront before they reach the
+// run's counters (flush_place_stats), so that tens of thousands of leaves
+// do not serialise on a few atomics.
+struct PlaceStats {
+  unsigned long long leafKeys[3];  // by leaf kind
+  uint32_t big;
+};
+
+AMS_DEV PlaceStats no_place_stats() { return PlaceStats{{0, 0, 0}, 0}; }
+
+// Call from uniform control flow (every lane of the wavefront).
+AMS_DEV void flush_place_stats(const Ws &w, const PlaceStats &ps) {
+  unsigned long long k[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) k[i] = wave_sum(ps.leafKeys[i]);
+  const uint32_t big = wave_sum(ps.big);
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (k[i]) atomicAdd(&w.ctr->leaf_keys[i], k[i]);
+    if (big) atomicAdd(&w.ctr->nbig, big);
+  }
+}
+
+AMS_DEV void push_leaf(const Ws &w, Seg s, PlaceStats &ps) {
   uint32_t slot = atomicAdd(&w.ctr->nleaf, 1u);
-  if (slot < w.capLeaf) w.leaves[slot] = s; else atomicOr(&w.ctr->overflow, 1u);
+  if (slot < w.capLeaf) w.leaves[slot] = s; else raise_error(w.ctr, 1u);
+  const uint32_t kind = seg_kind(s.meta);
+  ps.leafKeys[kind < 3 ? kind : 0] += s.size;
+  ps.big += kind == LEAF_BIG ? 1u : 0u;
 }
 
 // A root or child of N keys entering level lv: a leaf when it fits the base
@@ -150,14 +201,14 @@ AMS_DEV void push_leaf(const Ws &w, Seg s) {
 // active subproblem of level lv.
 AMS_DEV void place_subproblem(const Ws &w, const LevTable &lt, uint32_t L, uint32_t lv,
                               uint32_t off, uint32_t N, uint32_t root, uint32_t buf, bool inplace,
-                              uint32_t C) {
+                              uint32_t C, PlaceStats &ps) {
   if (N == 0) return;
   if (N <= C) {
-    push_leaf(w, Seg{off, N, root, make_meta(buf, LEAF_REG, 0, 0, 0)});
+    push_leaf(w, Seg{off, N, root, make_meta(buf, LEAF_REG, 0, 0, 0)}, ps);
     return;
   }
   if (lv >= L) {
-    push_leaf(w, Seg{off, N, root, make_meta(buf, LEAF_BIG, 0, 0, 0)});
+    push_leaf(w, Seg{off, N, root, make_meta(buf, LEAF_BIG, 0, 0, 0)}, ps);
     return;
   }
   const Lev &l = lt.l[lv];
@@ -165,7 +216,7 @@ AMS_DEV void place_subproblem(const Ws &w, const LevTable &lt, uint32_t L, uint3
   seg_shape(N, C, l.shrink != 0, l.rmax, l.b, l.a, l.Scap, logr, logm, S);
   uint32_t slot = atomicAdd(&w.ctr->nact[lv], 1u);
   Seg s{off, N, root, make_meta(buf, 0, dst_for(buf, inplace, L, lv), logm, logr)};
-  if (slot < w.capAct[lv]) w.act[lv][slot] = s; else atomicOr(&w.ctr->overflow, 1u);
+  if (slot < w.capAct[lv]) w.act[lv][slot] = s; else raise_error(w.ctr, 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -181,6 +232,7 @@ __global__ void k_reset(Ws w) {
 __global__ void k_init_roots(Ws w, LevTable lt, uint32_t L, uint32_t C, int mode, Root single,
                              const char *kin, const uint32_t *vin, char *kout, uint32_t *vout,
                              const uint64_t *offs, uint32_t kw) {
+  PlaceStats ps = no_place_stats();
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < w.nroots;
        i += gridDim.x * blockDim.x) {
     Root R;
@@ -198,8 +250,10 @@ __global__ void k_init_roots(Ws w, LevTable lt, uint32_t L, uint32_t C, int mode
       R = w.roots[i];
     }
     if (mode != 2) w.roots[i] = R;
-    place_subproblem(w, lt, L, 0, 0, (uint32_t)R.n, i, BUF_IN, root_inplace(R), C);
+    place_subproblem(w, lt, L, 0, 0, (uint32_t)R.n, i, BUF_IN, root_inplace(R), C, ps);
   }
+  flush_place_stats(w, ps);
+  if (blockIdx.x == 0 && threadIdx.x == 0) w.ctr->L = L;
 }
 
 // Prefix sums over the active list of a level: tiles, tile blocks, sample blocks.
@@ -208,12 +262,14 @@ __global__ void __launch_bounds__(1024) k_plan(Ws w, Lev lv) {
   const uint32_t tid = threadIdx.x;
   uint32_t n = w.ctr->nact[lv.level];
   if (n > w.capAct[lv.level]) {
-    if (tid == 0) atomicOr(&w.ctr->overflow, 2u);
+    if (tid == 0) raise_error(w.ctr, 2u);
     n = w.capAct[lv.level];
   }
   const Seg *act = w.act[lv.level];
+  unsigned long long keys = 0;
   for (uint32_t i = tid; i < n; i += 1024) {
     Seg s = act[i];
+    keys += s.size;
     uint32_t tiles = (s.size + lv.TC - 1) / lv.TC;
     w.tileStart[i] = tiles;
     w.blkStart[i] = (tiles + lv.TB - 1) / lv.TB;
@@ -221,6 +277,9 @@ __global__ void __launch_bounds__(1024) k_plan(Ws w, Lev lv) {
     seg_shape(s.size, lv.C, lv.shrink != 0, lv.rmax, lv.b, lv.a, lv.Scap, logr, logm, S);
     w.sampStart[i] = S / 256;
   }
+  keys = wave_sum(keys);
+  if ((tid & 63u) == 0 && keys) atomicAdd(&w.ctr->lv_keys[lv.level], keys);
+  if (tid == 0) w.ctr->lv_sub[lv.level] = n;
   __syncthreads();
   uint32_t tt = block_exscan<1024>(w.tileStart, n, tmp);
   uint32_t tb = block_exscan<1024>(w.blkStart, n, tmp);
@@ -233,7 +292,8 @@ __global__ void __launch_bounds__(1024) k_plan(Ws w, Lev lv) {
     // level processes nothing (and the overflow flag is raised) rather than
     // index past its tables
     const bool over = tt > w.capTile || tb > w.capBlk || ts > w.capSBlk;
-    if (over) atomicOr(&w.ctr->overflow, 4u);
+    if (over) raise_error(w.ctr, 4u);
+    w.ctr->lv_tiles[lv.level] = tt;
     w.ctr->P = over ? 0 : n;
     w.ctr->ntile = over ? 0 : tt;
     w.ctr->nblk = over ? 0 : tb;
@@ -553,7 +613,8 @@ AMS_DEV Greedy greedy_scan(const uint32_t *wgt, uint32_t nb, uint32_t L, uint32_
 // L* for weights wgt[0..nb) and at most r groups, by a block of NT threads.
 // red: 2*NT/64 words of LDS.
 template <int NT>
-AMS_DEV uint32_t optimal_load(const uint32_t *wgt, uint32_t nb, uint32_t r, uint32_t *red) {
+AMS_DEV uint32_t optimal_load(const uint32_t *wgt, uint32_t nb, uint32_t r, uint32_t *red,
+                              uint32_t *Wout = nullptr) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr uint32_t NW = NT / 64;
   uint32_t W = 0, mx = 0;
@@ -575,6 +636,7 @@ AMS_DEV uint32_t optimal_load(const uint32_t *wgt, uint32_t nb, uint32_t r, uint
     mx = max(mx, red[NW + q]);
   }
   __syncthreads();
+  if (Wout) *Wout = W;
   uint32_t avg = (uint32_t)(((uint64_t)W + r - 1) / r);
   uint32_t lo = max(mx, avg), hi = avg + mx;
   while (lo < hi) {
@@ -756,10 +818,11 @@ __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
       p.wgt[id] = (fin || id >= NB) ? 0u : p.tot[id];
     }
     __syncthreads();
-    const uint32_t L = optimal_load<256>(p.wgt, NB, r, p.red);
+    uint32_t Wreg = 0;  // keys outside final children
+    const uint32_t L = optimal_load<256>(p.wgt, NB, r, p.red, &Wreg);
     uint32_t nch = build_children<256>(p, NB, L, CH);
     if (nch > CH || p.aux[NB] != N) {  // cannot happen: at most 3r = CH children
-      if (tid == 0) atomicOr(&w.ctr->overflow, 8u);
+      if (tid == 0) raise_error(w.ctr, 8u);
       nch = 0;
     }
     if (w.dbgHist && lv.level == 0 && i == 0) {
@@ -815,12 +878,15 @@ __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
       gF[2 * c + 1] = (uint16_t)(a < b ? b : p.first[c]);
       gS[c] = p.start[c];
     }
+    PlaceStats ps = no_place_stats();
+    uint32_t maxChild = 0;
     for (uint32_t c = tid; c < nch; c += 256) {
       const uint32_t off = s.off + p.start[c], size = p.sz[c];
       uint32_t cd;
       if (p.kind[c] == CHILD_REG) {
         cd = dst;
-        place_subproblem(w, lt, lv.L, lv.level + 1, off, size, s.root, cd, inplace, lv.C);
+        maxChild = size > maxChild ? size : maxChild;
+        place_subproblem(w, lt, lv.L, lv.level + 1, off, size, s.root, cd, inplace, lv.C, ps);
       } else {
         cd = finToOut ? BUF_OUT : dst;
         if (cd != BUF_OUT) {
@@ -832,13 +898,29 @@ __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
             if (slot + q < w.capLeaf)
               w.leaves[slot + q] = Seg{off + o, sz, s.root, make_meta(cd, LEAF_COPY, 0, 0, 0)};
             else
-              atomicOr(&w.ctr->overflow, 1u);
+              raise_error(w.ctr, 1u);
           }
+          ps.leafKeys[LEAF_COPY] += size;
         }
       }
       gD[c] = (uint8_t)(cd | (p.kind[c] << 4));
     }
-    if (tid == 0) w.nch[i] = nch;
+    // statistics: leaves, the largest regular child, keys in final children
+    // and the imbalance L* / ceil(W / r) of the grouping (Section 6, lemma on
+    // the largest group)
+    flush_place_stats(w, ps);
+    maxChild = wave_max(maxChild);
+    if ((tid & 63u) == 0 && maxChild) atomicMax(&w.ctr->lv_maxchild[lv.level], maxChild);
+    if (tid == 0) {
+      w.nch[i] = nch;
+      if (N > Wreg) atomicAdd(&w.ctr->lv_final[lv.level], (unsigned long long)(N - Wreg));
+      if (Wreg) {
+        const uint32_t avg = (Wreg + r - 1) / r;
+        const uint32_t q = (uint32_t)(((uint64_t)L << 16) / avg);
+        atomicMax(&w.ctr->lv_imb_max[lv.level], q);
+        atomicAdd(&w.ctr->lv_imb_sum[lv.level], (unsigned long long)q);
+      }
+    }
     __syncthreads();
   }
 }
@@ -1057,7 +1139,7 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
         const uint32_t c = stC[q];
         const uint32_t rel = sBase[c] + (q - sL[c]);
         if (rel >= s.size) {  // defensive: tables inconsistent; never write outside
-          atomicOr(&w.ctr->overflow, 16u);
+          raise_error(w.ctr, 16u);
           continue;
         }
         const uint32_t d = s.off + rel;
@@ -1278,7 +1360,7 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
           const K *base = kptr<K>(w, R, cd & 15u) + s.off + sBase[c];
           d = ((uint64_t)(uintptr_t)base - (uint64_t)lc * sizeof(K)) | (uint64_t)(cd >> 4);
         } else {
-          atomicOr(&w.ctr->overflow, 16u);
+          raise_error(w.ctr, 16u);
         }
         sDst[c] = d;
         sBase[c] += nc;
@@ -1458,7 +1540,7 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_pairs(Ws w, Lev lv) 
         if ((uint64_t)sBase[c] + tot <= s.size) {
           sRel[c] = s.off + sBase[c] - sL[c];
         } else {  // would overrun the subproblem: dropped and flagged
-          atomicOr(&w.ctr->overflow, 16u);
+          raise_error(w.ctr, 16u);
           sRel[c] = 0xFFFFFFFFu;
         }
         sBase[c] += tot;
@@ -2267,7 +2349,7 @@ __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint3
     const Seg L = w.leaves[li];
     const Root R = w.roots[L.root];
     if ((uint64_t)L.off + L.size > R.n) {  // defensive: never touch memory outside the root
-      if (tid == 0) atomicOr(&w.ctr->overflow, 32u);
+      if (tid == 0) raise_error(w.ctr, 32u);
       continue;
     }
     const uint32_t kind = seg_kind(L.meta), buf = seg_buf(L.meta);
@@ -2415,6 +2497,71 @@ int trace_stop(ams_trace_entry *out, int max) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// ---------------------------------------------------------------------------
+// Device errors and run statistics
+// ---------------------------------------------------------------------------
+ams_status device_errors(hipStream_t s, uint32_t *bits, bool clear) {
+  uint32_t v = 0;
+  hipError_t e = hipMemcpyFromSymbolAsync(&v, HIP_SYMBOL(g_dev_errors), 4, 0,
+                                          hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && clear && v) {
+    const uint32_t zero = 0;
+    e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_dev_errors), &zero, 4, 0, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  if (e != hipSuccess) {
+    set_error("reading the device error word: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  if (bits) *bits = v;
+  return AMS_OK;
+}
+
+size_t run_error_offset() { return offsetof(Ctr, overflow); }
+
+// Errors raised by the run whose counters sit at the start of ws (waits for s).
+ams_status run_errors(const void *ws, hipStream_t s, uint32_t *bits) {
+  uint32_t v = 0;
+  hipError_t e = hipMemcpyAsync(&v, (const char *)ws + offsetof(Ctr, overflow), 4,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    set_error("reading the run's error word: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  *bits = v;
+  return AMS_OK;
+}
+
+ams_status run_stats(const void *ws, hipStream_t s, ams_run_stats *out) {
+  Ctr c;
+  hipError_t e = hipMemcpyAsync(&c, ws, sizeof c, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    set_error("reading the run's counters: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  memset(out, 0, sizeof *out);
+  out->device_errors = c.overflow;
+  out->levels = c.L;
+  for (uint32_t l = 0; l < MAXLEV && l < 4; ++l) {
+    out->subproblems[l] = c.lv_sub[l];
+    out->keys[l] = c.lv_keys[l];
+    out->final_keys[l] = c.lv_final[l];
+    out->max_child[l] = c.lv_maxchild[l];
+    out->tiles[l] = c.lv_tiles[l];
+    out->imbalance_max[l] = c.lv_imb_max[l] / 65536.0;
+    out->imbalance_mean[l] = c.lv_sub[l] ? (double)c.lv_imb_sum[l] / 65536.0 / c.lv_sub[l] : 0.0;
+  }
+  out->leaves = c.nleaf;
+  out->big_leaves = c.nbig;
+  out->leaf_keys = c.leaf_keys[LEAF_REG];
+  out->copy_keys = c.leaf_keys[LEAF_COPY];
+  out->big_keys = c.leaf_keys[LEAF_BIG];
+  return AMS_OK;
+}
+
 ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t nroots,
                      uint64_t n_single, const ams_params *p) {
   memset(&pl, 0, sizeof pl);
@@ -2429,8 +2576,9 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
   uint64_t total = 0, mx = 0;
   for (uint32_t i = 0; i < nroots; ++i) {
     uint64_t n = sizes ? sizes[i] : n_single;
-    if (n >= (1ull << 32)) {
-      set_error("segment of %llu elements: sizes must be below 2^32", (unsigned long long)n);
+    if (n > AMS_MAX_SEGMENT) {
+      set_error("segment of %llu elements: at most %llu are supported", (unsigned long long)n,
+                (unsigned long long)AMS_MAX_SEGMENT);
       return AMS_EUNSUPPORTED;
     }
     total += n;
@@ -2491,8 +2639,10 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
   // tiles of 64 Ki keys once there are at least 2048 of them (8 per CU):
   // fewer per-tile histograms and tile starts to reduce and scan
   uint32_t TC = (p && p->tile_keys) ? p->tile_keys : (keysBig >= (1ull << 27) ? 65536 : 32768);
-  if (TC % 4096 || TC == 0) {
-    set_error("tile_keys must be a positive multiple of 4096 (got %u)", TC);
+  // (with segments of at most 2^32 - 2^20 keys, tile bounds up to 2^19 keys
+  // stay below 2^32 in the kernels' 32-bit tile arithmetic)
+  if (TC % 4096 || TC == 0 || TC > (1u << 19)) {
+    set_error("tile_keys must be a positive multiple of 4096, at most 2^19 (got %u)", TC);
     return AMS_EINVAL;
   }
   const uint32_t Scap = 65536 / pl.kw;
@@ -2551,6 +2701,9 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     P = nextP;
   }
   pl.capLeaf = (uint32_t)std::min<uint64_t>(leaves + total / C + 2, 0xFFFFFFF0ull);
+  // test hook: a leaf table of one entry, so that a sort needing more leaves
+  // takes the device's table-overflow path (raises AMS_DEVERR_TABLE)
+  if (pl.flags & AMS_FLAG_TEST_TINY_TABLES) pl.capLeaf = 1;
   uint32_t capAct = 1, capTile = 1, capBlk = 1, capS = 1, maxHS = 2, maxCH = 3, maxM = 2, maxS = 256;
   for (uint32_t l = 0; l < L; ++l) {
     const LevelShape &ls = pl.lev[l];
@@ -2577,10 +2730,12 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     o = align256(o + bytes);
     return at;
   };
+  // the run's counters come first, so ams_workspace_stats finds them at the
+  // start of any workspace
+  pl.o_ctr = take(sizeof(Ctr));
   pl.o_tmpK = take(L ? total * pl.kw : 0);
   pl.o_tmpV = take(L && pay ? total * 4 : 0);
   pl.o_roots = take((size_t)nroots * sizeof(Root));
-  pl.o_ctr = take(sizeof(Ctr));
   for (uint32_t l = 0; l <= MAXLEV; ++l)
     pl.o_act[l] = take(l < L ? (size_t)pl.lev[l].P * sizeof(Seg) : 0);
   pl.o_leaves = take((size_t)pl.capLeaf * sizeof(Seg));

@@ -34,6 +34,7 @@ namespace ams {
 ams_status run_plan_ex(const Plan &pl, void *ws, const RootSource &src, hipStream_t s,
                        uint32_t *dbg_hist, uint32_t *dbg_children, uint32_t *dbg_nchild,
                        const void *given_splitters, bool shrink_last);
+size_t run_error_offset();
 }
 
 using namespace ams;
@@ -76,6 +77,7 @@ struct StreamState {
   bool busy = false;
   Root *h_roots = nullptr;  // pinned staging of the root table
   size_t cap_roots = 0;
+  uint32_t *h_err = nullptr;  // pinned copy of the running batch's device error bits
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -108,6 +110,7 @@ struct ams_server {
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   uint64_t max_batch_keys = 1ull << 28;
   uint32_t max_batch_reqs = 1024;
+  uint32_t inject_alloc_failures = 0;  // test hook: batches left to fail
 
   size_t workspace_for(ams_key_t t, bool pay, const std::vector<uint64_t> &sizes) {
     Plan pl;
@@ -173,6 +176,14 @@ struct ams_server {
     }
   }
 
+  // Called with mu released (launch): consumes one injected failure.
+  bool take_injected_failure() {
+    std::lock_guard<std::mutex> g(mu);
+    if (!inject_alloc_failures) return false;
+    --inject_alloc_failures;
+    return true;
+  }
+
   void fail(Request &r, ams_status st) {
     r.state = DONE;
     r.st.status = st;
@@ -229,6 +240,7 @@ struct ams_server {
     ResultBlock blk;
     Plan pl;
     st = make_plan(pl, (int)type, pay, sizes.data(), (uint32_t)sizes.size(), 0, nullptr);
+    if (!st && take_injected_failure()) st = AMS_ENOMEM;
     if (!st && hipMallocAsync(&blk.ptr, results ? results : 256, s) != hipSuccess) st = AMS_ENOMEM;
     if (!st && hipMallocAsync(&b.ws, pl.bytes, s) != hipSuccess) st = AMS_ENOMEM;
     if (!st && ss.cap_roots < pick.size()) {
@@ -270,6 +282,11 @@ struct ams_server {
       memset(&rs, 0, sizeof rs);
       rs.mode = 2;
       st = run_plan_ex(pl, b.ws, rs, s, nullptr, nullptr, nullptr, nullptr, true);
+      // the batch's device error bits (counters at the start of the
+      // workspace), read back with the batch
+      if (!st && hipMemcpyAsync(ss.h_err, (char *)b.ws + run_error_offset(), 4,
+                                hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = AMS_EHIP;
       (void)hipEventRecord(ss.ev1, s);
     }
     const double tl = now_us(t0);
@@ -304,11 +321,13 @@ struct ams_server {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, ss.ev0, ss.ev1);
       const double td = now_us(t0);
+      // a device error of the batch invalidates every result in it
+      const ams_status bst = *ss.h_err ? AMS_EDEVICE : AMS_OK;
       for (uint64_t t : b.tickets) {
         Request &r = reqs[t];
         if (r.state == DONE) continue;
         r.state = DONE;
-        r.st.status = AMS_OK;
+        r.st.status = bst;
         r.st.t_done_us = td;
         r.st.gpu_ms = ms;
         --outstanding;
@@ -407,18 +426,21 @@ ams_server *ams_server_create(int device, size_t hbm_budget, uint32_t max_pendin
   for (uint32_t i = 0; i < ns; ++i) {
     StreamState ss;
     if (hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreate(&ss.ev0) != hipSuccess || hipEventCreate(&ss.ev1) != hipSuccess) {
-      set_error("hipStreamCreate / hipEventCreate failed");
+        hipEventCreate(&ss.ev0) != hipSuccess || hipEventCreate(&ss.ev1) != hipSuccess ||
+        hipHostMalloc((void **)&ss.h_err, 4, 0) != hipSuccess) {
+      set_error("hipStreamCreate / hipEventCreate / hipHostMalloc failed");
       if (st) *st = AMS_EHIP;
       s->streams.push_back(ss);
       for (StreamState &x : s->streams) {
         if (x.s) (void)hipStreamDestroy(x.s);
         if (x.ev0) (void)hipEventDestroy(x.ev0);
         if (x.ev1) (void)hipEventDestroy(x.ev1);
+        if (x.h_err) (void)hipHostFree(x.h_err);
       }
       delete s;
       return nullptr;
     }
+    *ss.h_err = 0;
     s->streams.push_back(ss);
   }
   s->worker = std::thread([s] { s->loop(); });
@@ -431,8 +453,9 @@ ams_status ams_submit(ams_server *srv, ams_key_t t, const void *d_keys, const ui
     set_error("bad arguments");
     return AMS_EINVAL;
   }
-  if (n >= (1ull << 32)) {
-    set_error("request of %zu keys: sizes must be below 2^32", n);
+  if (n > AMS_MAX_SEGMENT) {
+    set_error("request of %zu keys: at most %llu are supported", n,
+              (unsigned long long)AMS_MAX_SEGMENT);
     return AMS_EUNSUPPORTED;
   }
   std::unique_lock<std::mutex> lk(srv->mu);
@@ -544,6 +567,7 @@ void ams_server_destroy(ams_server *srv) {
     (void)hipStreamSynchronize(x.s);
     (void)hipStreamDestroy(x.s);
     if (x.h_roots) (void)hipHostFree(x.h_roots);
+    if (x.h_err) (void)hipHostFree(x.h_err);
     (void)hipEventDestroy(x.ev0);
     (void)hipEventDestroy(x.ev1);
   }
@@ -552,24 +576,42 @@ void ams_server_destroy(ams_server *srv) {
 
 ams_status ams_result_copy(ams_server *srv, uint64_t ticket, void *d_keys, uint32_t *d_vals,
                            void *stream) {
+  if (!srv) return AMS_EINVAL;
   void *k = nullptr;
   uint32_t *v = nullptr;
-  ams_status st = ams_result(srv, ticket, &k, &v);
-  if (st) return st;
-  uint64_t n;
-  size_t kb;
+  uint64_t n = 0;
+  size_t kb = 0;
   {
+    // one lookup under the lock: a concurrent release cannot slip in between
     std::lock_guard<std::mutex> lk(srv->mu);
-    const Request &r = srv->reqs[ticket];
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return AMS_ENOTFOUND;
+    const Request &r = it->second;
+    if (r.state != DONE) {
+      set_error("request %llu has not finished", (unsigned long long)ticket);
+      return AMS_EAGAIN;
+    }
+    if (r.st.status) return r.st.status;
+    k = r.out_k;
+    v = r.out_v;
     n = r.n;
     kb = kbytes(r.type);
+    if (!n) return AMS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // the copies are enqueued under the lock, so the ticket cannot be
+    // released between the lookup and the copies
+    if (d_keys && hipMemcpyAsync(d_keys, k, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return AMS_EHIP;
+    if (d_vals && v && hipMemcpyAsync(d_vals, v, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return AMS_EHIP;
   }
-  if (!n) return AMS_OK;
-  hipStream_t s = (hipStream_t)stream;
-  if (d_keys && hipMemcpyAsync(d_keys, k, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return AMS_EHIP;
-  if (d_vals && v && hipMemcpyAsync(d_vals, v, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return AMS_EHIP;
+  return AMS_OK;
+}
+
+ams_status ams_server_inject_alloc_failures(ams_server *srv, uint32_t count) {
+  if (!srv) return AMS_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->inject_alloc_failures = count;
   return AMS_OK;
 }
 

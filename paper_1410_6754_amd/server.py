@@ -69,6 +69,10 @@ class Server:
         check(lib().ams_result(self._h, ticket, ctypes.byref(k), ctypes.byref(v)))
         return k.value, v.value
 
+    def inject_alloc_failures(self, count: int):
+        """Test hook: the next ``count`` batches fail as if out of memory."""
+        check(lib().ams_server_inject_alloc_failures(self._h, count))
+
     def release(self, ticket: int):
         # the result may still be read by work queued on the current stream
         # (result() copies there); the library frees in order on its own

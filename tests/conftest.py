@@ -27,3 +27,15 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _no_device_errors(request):
+    """Every GPU test ends with the device's error word clear: a table bound
+    exceeded anywhere in the library fails the test that caused it."""
+    yield
+    if "gpu" not in request.keywords or not _gpu_available():
+        return
+    from paper_1410_6754_amd import api
+    bits = api.device_errors(clear=True)
+    assert bits == 0, "device error bits 0x%x raised during the test" % bits

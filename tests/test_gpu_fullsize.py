@@ -1,0 +1,125 @@
+"""Full-size parity: the benchmark's own workloads and plans, element by
+element against the oracle (its parallel mergesort on the host's cores).
+
+* 2^28 uniform uint64 keys with the benchmark's plan (two levels, k = 256,
+  b = 4, 64 Ki-key tiles), and the same keys sorted and reversed: one
+  multiset, so the oracle's output is the expected result of all three;
+* 2^27 (uint64 key, uint32 index) pairs: 2^10 distinct values, Zipf(1.1)
+  and all-equal keys, with the default plan;
+* 2^20 uniform uint64 keys with one level, k = 256, b = 1, a = 16 and
+  base-case cutoff 1024.
+Inputs come from the same seeded generators and parameters as bench.py.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import bench
+import oracle
+from gpu_util import assert_same_bits, log, to_dev
+from oracle import checkers
+from paper_1410_6754_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def threads():
+    n = len(os.sched_getaffinity(0))
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1410_6754_amd import api as A
+    return A
+
+
+def workload(name):
+    n, kt, dist, pay, params, cfg = bench.WORKLOADS[name]
+    return n, kt, dist, pay, params, cfg
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def u64_2p28():
+    """The default workload's keys and the oracle's sorted output."""
+    n, kt, dist, _, _, cfg = workload("uniform_u64_2^28")
+    keys = W.keys(kt, n, W.rng_for(cfg), dist)
+    log("oracle: 2^28 uint64 keys on %d threads" % threads())
+    perm = oracle.oracle_sort_perm_parallel(kt, keys, threads())
+    return keys, keys[perm.astype(np.int64)]
+
+
+def run_keys(api, name, keys):
+    n, kt, _, _, params, _ = workload(name)
+    p = api.make_params(**params)
+    ws = api.alloc_workspace(api.workspace_bytes(kt, n, False, p))
+    d = to_dev(keys)
+    out = api.sort_keys(d, params=p, workspace=ws)
+    st = api.workspace_stats(ws)
+    got = host(out)
+    del d, out, ws
+    return got, st
+
+
+@pytest.mark.parametrize("name", ["uniform_u64_2^28", "sorted_u64_2^28", "reversed_u64_2^28"])
+def test_bench_plan_2p28(api, u64_2p28, name):
+    keys, want = u64_2p28
+    if name.startswith("sorted"):
+        keys = want  # the unique sorted order of the same keys
+    elif name.startswith("reversed"):
+        keys = want[::-1].copy()
+    log("%s on the GPU" % name)
+    got, st = run_keys(api, name, keys)
+    # the plan the benchmark times: two levels of 1024 buckets, 64 Ki tiles
+    assert st["levels"] == 2 and st["device_errors"] == 0
+    assert st["tiles"][0] == (1 << 28) // 65536
+    assert st["keys"][0] == 1 << 28 and st["keys"][1] == 1 << 28
+    assert st["leaf_keys"] + st["copy_keys"] + st["big_keys"] == 1 << 28
+    assert_same_bits(got, want, name)
+    assert checkers.check_keys(W.KEY_U64, keys, got) is None
+
+
+@pytest.mark.parametrize("name", ["pairs_few_2^27", "pairs_zipf_2^27", "pairs_equal_2^27"])
+def test_bench_plan_pairs_2p27(api, name):
+    n, kt, dist, pay, params, cfg = workload(name)
+    assert pay
+    keys = W.keys(kt, n, W.rng_for(cfg), dist)
+    vals = np.arange(n, dtype=np.uint32)
+    log("%s: oracle on %d threads" % (name, threads()))
+    perm = oracle.oracle_sort_perm_parallel(kt, keys, threads()).astype(np.int64)
+    log("%s on the GPU" % name)
+    p = api.make_params(**params)
+    ws = api.alloc_workspace(api.workspace_bytes(kt, n, True, p))
+    ok, ov = api.sort_pairs(to_dev(keys), to_dev(vals), params=p, workspace=ws)
+    st = api.workspace_stats(ws)
+    gk, gv = host(ok), host(ov)
+    assert st["device_errors"] == 0
+    assert_same_bits(gk, keys[perm], name + " keys")
+    assert_same_bits(gv, perm.astype(np.uint32), name + " payload")
+    assert checkers.check_pairs(kt, keys, gk, gv) is None
+
+
+def test_bench_plan_config1(api):
+    name = "uniform_u64_2^20"
+    n, kt, dist, _, params, cfg = workload(name)
+    assert params == dict(levels=1, k=256, overpartition_b=1, samples_per_bucket=16,
+                          base_cutoff=1024)
+    keys = W.keys(kt, n, W.rng_for(cfg), dist)
+    want, _ = oracle.oracle_sort(kt, keys)
+    log("%s on the GPU" % name)
+    got, st = run_keys(api, name, keys)
+    assert st["levels"] == 1 and st["subproblems"][0] == 1 and st["subproblems"][1] == 0
+    assert st["leaf_keys"] + st["big_keys"] == n
+    assert_same_bits(got, want, name)
