@@ -102,25 +102,30 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(keys: np.ndarray, kt: int, vals, sample_n: int, single_n: int):
+def cpu_baseline(keys: np.ndarray, kt: int, vals, sample_n: int, single_n: int, runs: int = 3):
     """The oracle's mergesort timed on the host: the plain parallel form on
-    all host threads over the first sample_n keys (the reported value), and
-    the single-threaded form over the first single_n keys."""
+    all host threads over the first sample_n keys (median of `runs` calls:
+    the reported value), and the single-threaded form over the first
+    single_n keys (one call)."""
     import oracle
     threads = host_threads()
     sample = np.ascontiguousarray(keys[:sample_n])
-    t0 = time.perf_counter()
-    oracle.oracle_sort_perm_parallel(kt, sample, threads)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(max(1, runs)):
+        t0 = time.perf_counter()
+        oracle.oracle_sort_perm_parallel(kt, sample, threads)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     single = np.ascontiguousarray(keys[:single_n])
     sv = None if vals is None else np.ascontiguousarray(vals[:single_n])
     t1 = time.perf_counter()
     oracle.oracle_sort(kt, single, sv)
     dt1 = time.perf_counter() - t1
     return {"value": sample_n / dt / 1e9, "unit": "GKeys/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d keys of the workload (2^%d), one call of the oracle's plain "
-                      "parallel mergesort (per-thread chunks, then a pairwise merge tree) on %d "
-                      "host threads, %.2f s" % (sample_n, int(np.log2(sample_n)), threads, dt),
+            "sample": "first %d keys of the workload (2^%d), median of %d calls of the oracle's "
+                      "plain parallel mergesort (per-thread chunks, then a pairwise merge tree) "
+                      "on %d host threads: %s s" % (sample_n, int(np.log2(sample_n)), len(times),
+                                                   threads, ", ".join("%.2f" % t for t in times)),
             "cpu_model": cpu_model(),
             "single_thread": {"value": single_n / dt1 / 1e9, "unit": "GKeys/s", "cores": 1,
                               "sample": "first %d keys (2^%d), the textbook mergesort, %.2f s"
@@ -141,7 +146,11 @@ def main() -> int:
                     help="keys the parallel oracle sorts (log2)")
     ap.add_argument("--cpu-single-log2", type=int, default=25,
                     help="keys the single-threaded oracle sorts (log2)")
+    ap.add_argument("--cpu-runs", type=int, default=3,
+                    help="runs of the parallel oracle (the median is reported)")
     ap.add_argument("--trace-file", default=None, help="write the per-kernel table here")
+    ap.add_argument("--params", default=None,
+                    help="JSON object of ams_params fields that replace the workload's (sweeps)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy three times (the known-size "
                          "kernel that scales the HBM byte counters), then exit")
@@ -172,6 +181,8 @@ def main() -> int:
         return bench_serving(args)
 
     n, kt, dist, pay, pkw, cfg = WORKLOADS[args.workload]
+    if args.params:
+        pkw = dict(pkw, **json.loads(args.params))
     w = key_bytes(kt) + (4 if pay else 0)
     print("bench: generating %s (n=%d)" % (args.workload, n), file=sys.stderr, flush=True)
     rng = W.rng_for(cfg)
@@ -226,12 +237,10 @@ def main() -> int:
     print("bench: timed %d steps, %.3f ms/step (wall %.3f s)" % (args.steps, ms_per_step, wall),
           file=sys.stderr, flush=True)
 
-    # correctness of the last output: sorted (ord order) -- cheap check on GPU
-    if kt == W.KEY_U64:
-        o = d_out.view(torch.int64) ^ torch.iinfo(torch.int64).min
-        verified = bool((o[1:] >= o[:-1]).all().item())
-    else:
-        verified = None
+    # statistics of the sort (every step runs the same plan on the same keys)
+    st = api.workspace_stats(ws, stream=stream)
+    verified = verify_against_device_sort(kt, d_keys, d_out, d_vout)
+    _log("output %s the device reference sort" % ("matches" if verified else "DIFFERS FROM"))
 
     # per-kernel table (levels folded together)
     per = {}
@@ -240,47 +249,41 @@ def main() -> int:
         d = per.setdefault(base, {"launches": 0, "total_ms": 0.0})
         d["launches"] += e["launches"]
         d["total_ms"] += e["total_ms"]
-    alg_bytes = {"scatter": 2 * w * n, "finish": 2 * w * n, "count": key_bytes(kt) * n}
-    dom = max(per, key=lambda k: per[k]["total_ms"])
-    avg_ms = per[dom]["total_ms"] / per[dom]["launches"]
-    if dom in alg_bytes:
-        achieved = alg_bytes[dom] / (avg_ms * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom, args.workload),
-                "algorithmic_bytes_per_launch": alg_bytes[dom], "avg_launch_ms": round(avg_ms, 4)}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": None, "traffic": None, "avg_launch_ms": round(avg_ms, 4)}
     kernels = {k: {"launches": v["launches"], "avg_ms": round(v["total_ms"] / v["launches"], 4),
                    "share": round(v["total_ms"] / sum(x["total_ms"] for x in per.values()), 4)}
                for k, v in sorted(per.items(), key=lambda kv: -kv[1]["total_ms"])}
-    # every HBM pass against the peak: the partition passes (count reads the
-    # keys, scatter reads and writes them) and the base case (reads and
-    # writes them once); algorithmic bytes per launch over its average time
-    ceiling = copy_ceiling()
-    passes = {}
-    for k in ("count", "scatter", "finish"):
-        if k in per:
-            am = per[k]["total_ms"] / per[k]["launches"]
-            gbs = alg_bytes[k] / (am * 1e-3) / 1e9
-            passes[k] = {"avg_launch_ms": round(am, 4), "algorithmic_bytes_per_launch": alg_bytes[k],
-                         "GB_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
-                         "frac_of_copy": round(gbs / ceiling["GB_per_s"], 4)}
-    if "count" in passes and "scatter" in passes:
-        # one partition level as a whole: count reads the keys, scatter reads
-        # and writes them (3w bytes per key moved by the implementation, of
-        # which 2w are the level's algorithmic read and write)
-        lm = passes["count"]["avg_launch_ms"] + passes["scatter"]["avg_launch_ms"]
-        ib = alg_bytes["count"] + alg_bytes["scatter"]
-        passes["partition_level"] = {
-            "ms": round(lm, 4), "implementation_bytes": ib,
-            "GB_per_s": round(ib / (lm * 1e-3) / 1e9, 1),
-            "frac_of_peak": round(ib / (lm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "frac_of_copy": round(ib / (lm * 1e-3) / 1e9 / ceiling["GB_per_s"], 4)}
+    ceiling = copy_ceiling(api)
+    passes, alg = pass_table(trace, st, w, key_bytes(kt), args.steps, ceiling["GB_per_s"])
+    # the roofline object: the kernel with the largest time per sort, its
+    # algorithmic bytes (keys that took part in its launches) per launch over
+    # its average launch duration
+    dom = max(per, key=lambda k: per[k]["total_ms"])
+    avg_ms = per[dom]["total_ms"] / per[dom]["launches"]
+    if dom in alg and alg[dom]["ms"] > 0:
+        a = alg[dom]
+        achieved = a["bytes"] / (a["ms"] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom, args.workload),
+                "algorithmic_bytes_per_launch": int(a["bytes"] / a["launches"]),
+                "avg_launch_ms": round(a["ms"] / a["launches"], 4),
+                "launches_with_work_per_step": a["launches"] // args.steps}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": None, "traffic": None, "avg_launch_ms": round(avg_ms, 4)}
+    levels = [{"level": l, "subproblems": st["subproblems"][l], "keys": st["keys"][l],
+               "final_keys": st["final_keys"][l], "max_child": st["max_child"][l],
+               "tiles": st["tiles"][l],
+               "imbalance_max": round(st["imbalance_max"][l], 4),
+               "imbalance_mean": round(st["imbalance_mean"][l], 4)}
+              for l in range(st["levels"])]
+    leaves = {"leaves": st["leaves"], "big_leaves": st["big_leaves"], "leaf_keys": st["leaf_keys"],
+              "copy_keys": st["copy_keys"], "big_keys": st["big_keys"],
+              "device_errors": st["device_errors"]}
     if args.trace_file:
         with open(args.trace_file, "w") as f:
-            json.dump({"workload": args.workload, "trace": trace, "kernels": kernels}, f, indent=1)
+            json.dump({"workload": args.workload, "trace": trace, "kernels": kernels,
+                       "stats": st}, f, indent=1)
 
     cpu = None
     if not args.no_cpu:
@@ -288,7 +291,7 @@ def main() -> int:
         single_n = min(n, 1 << args.cpu_single_log2)
         print("bench: timing the oracle on %d keys (%d threads) and %d keys (1 thread)"
               % (sample_n, host_threads(), single_n), file=sys.stderr, flush=True)
-        cpu = cpu_baseline(keys, kt, vals, sample_n, single_n)
+        cpu = cpu_baseline(keys, kt, vals, sample_n, single_n, args.cpu_runs)
 
     value = n / (ms_per_step * 1e-3) / 1e9
     line = {
@@ -313,36 +316,126 @@ def main() -> int:
         "copy_ceiling": ceiling,
         "cpu_baseline": cpu,
         "kernels": kernels,
-        "verified_sorted": verified,
+        "levels": levels,
+        "leaves": leaves,
+        "verified": verified,
     }
     print(json.dumps(line))
     return 0
 
 
-def copy_ceiling():
-    """The practical HBM ceiling: a plain 2 GiB device-to-device copy (torch's
-    copy kernel, 4 GiB moved) timed with events, best of five."""
+def copy_ceiling(api):
+    """The practical HBM ceiling: the library's plain streaming copy of 2 GiB
+    (4 GiB moved), best of five, with torch's copy kernel beside it."""
     import torch
     src = torch.empty(1 << 28, dtype=torch.int64, device="cuda:0").fill_(1)
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    best = None
-    for _ in range(5):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        dst.copy_(src)
-        e1.record()
-        e1.synchronize()
-        t = e0.elapsed_time(e1)
-        best = t if best is None else min(best, t)
-    moved = 2 * src.numel() * src.element_size()
+    nbytes = src.numel() * src.element_size()
+    stream = torch.cuda.current_stream()
+    from paper_1410_6754_amd._lib import check, lib
+
+    def own():
+        check(lib().ams_device_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream.cuda_stream))
+
+    def best_of(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        return best
+
+    ms_own = best_of(own)
+    ok = bool(torch.equal(dst, src))
+    dst.zero_()
+    ms_torch = best_of(lambda: dst.copy_(src))
     del src, dst
     torch.cuda.empty_cache()
-    gbs = moved / (best * 1e-3) / 1e9
-    return {"kernel": "device-to-device copy of 2 GiB", "bytes_moved": moved, "ms": round(best, 4),
-            "GB_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    moved = 2 * nbytes
+    gbs = moved / (ms_own * 1e-3) / 1e9
+    gbt = moved / (ms_torch * 1e-3) / 1e9
+    return {"kernel": "ams_device_copy of 2 GiB (16 B per lane, 4 loads in flight)",
+            "bytes_moved": moved, "ms": round(ms_own, 4), "GB_per_s": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "copy_verified": ok,
+            "torch_copy_GB_per_s": round(gbt, 1)}
+
+
+def pass_table(trace, st, w: int, kw: int, steps: int, ceiling_gbs: float):
+    """Every HBM pass that had work, against the peak and the copy ceiling.
+
+    Level l's passes touch only the keys of its subproblems (st["keys"][l]):
+    keys placed in final children at earlier levels have dropped out, and a
+    level without subproblems launches its kernels on empty lists, which are
+    left out.  Count reads each key once (w_key bytes), the scatter reads and
+    writes it (2w), the base case reads and writes the keys of its leaves.
+    Returns (passes, per-kernel sums over the launches with work)."""
+    by_name = {e["name"]: e for e in trace}
+    passes = {}
+    alg = {}
+
+    def add(kernel, name, keys, per_key):
+        e = by_name.get(name)
+        if e is None or keys == 0:
+            return None
+        ms = e["total_ms"] / e["launches"]
+        b = per_key * keys
+        gbs = b / (ms * 1e-3) / 1e9
+        passes[name] = {"avg_launch_ms": round(ms, 4), "keys": keys,
+                        "algorithmic_bytes_per_launch": b, "GB_per_s": round(gbs, 1),
+                        "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                        "frac_of_copy": round(gbs / ceiling_gbs, 4)}
+        a = alg.setdefault(kernel, {"bytes": 0, "ms": 0.0, "launches": 0})
+        a["bytes"] += b * e["launches"]
+        a["ms"] += e["total_ms"]
+        a["launches"] += e["launches"]
+        return ms
+
+    for l in range(st["levels"]):
+        keys = st["keys"][l]
+        mc = add("count", "count.L%d" % l, keys, kw)
+        ms = add("scatter", "scatter.L%d" % l, keys, 2 * w)
+        if mc is not None and ms is not None:
+            # the level as a whole: 2w algorithmic bytes per key (read and
+            # write), 3w moved by this implementation (count reads once more)
+            lm = mc + ms
+            gbs = 2 * w * keys / (lm * 1e-3) / 1e9
+            passes["level.L%d" % l] = {
+                "ms": round(lm, 4), "keys": keys, "algorithmic_bytes": 2 * w * keys,
+                "implementation_bytes": (kw + 2 * w) * keys, "GB_per_s": round(gbs, 1),
+                "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                "implementation_GB_per_s": round((kw + 2 * w) * keys / (lm * 1e-3) / 1e9, 1)}
+    add("finish", "finish", st["leaf_keys"] + st["copy_keys"] + st["big_keys"], 2 * w)
+    return passes, alg
+
+
+def verify_against_device_sort(kt: int, d_keys, d_out, d_vout) -> bool:
+    """The sort's output equals torch's device sort of the same input, bit for
+    bit (keys mapped to signed integers of the same order; for pairs the
+    stable sort's indices are the expected payload, which is 0..n-1)."""
+    import torch
+    if kt == W.KEY_U64:
+        o = d_keys.view(torch.int64) ^ torch.iinfo(torch.int64).min
+    elif kt == W.KEY_U32:
+        o = d_keys.view(torch.int32) ^ torch.iinfo(torch.int32).min
+    else:
+        b = d_keys.view(torch.int32)
+        o = torch.where(b >= 0, b, (~b) ^ torch.iinfo(torch.int32).min)
+    sv, si = torch.sort(o, stable=True)
+    del sv
+    want = d_keys.view(o.dtype)[si]
+    ok = bool(torch.equal(want, d_out.view(o.dtype)))
+    if d_vout is not None:
+        ok = ok and bool(torch.equal(si.to(torch.int64), d_vout.to(torch.int64)))
+    del si, want, o
+    torch.cuda.empty_cache()
+    return ok
 
 
 def _log(msg):

@@ -224,6 +224,11 @@ typedef struct {
 ams_status ams_trace_start(void);
 int ams_trace_stop(ams_trace_entry *out, int max);
 
+/* Measurement aid: a plain streaming copy of `bytes` from d_src to d_dst
+ * (both 16-byte aligned, not overlapping), enqueued on `stream`.  Its rate is
+ * the practical HBM ceiling the level passes are measured against. */
+ams_status ams_device_copy(const void *d_src, void *d_dst, size_t bytes, void *stream);
+
 /* Library version string. */
 const char *ams_version(void);
 

@@ -154,6 +154,7 @@ EXPORTS = [
     ("ams_device_errors", _I, [_P, _P, _I]),
     ("ams_workspace_stats", _I, [_P, _P, _P]),
     ("ams_server_inject_alloc_failures", _I, [_P, _U32]),
+    ("ams_device_copy", _I, [_P, _P, _SZ, _P]),
 ]
 
 _lib = None

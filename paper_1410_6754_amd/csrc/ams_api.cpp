@@ -24,6 +24,7 @@ int trace_stop(ams_trace_entry *out, int max);
 ams_status device_errors(hipStream_t s, uint32_t *bits, bool clear);
 ams_status run_errors(const void *ws, hipStream_t s, uint32_t *bits);
 ams_status run_stats(const void *ws, hipStream_t s, ams_run_stats *out);
+ams_status device_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 }  // namespace ams
 
 using namespace ams;
@@ -126,6 +127,16 @@ ams_status ams_device_errors(void *stream, uint32_t *bits, int clear) {
     return AMS_EINVAL;
   }
   return device_errors((hipStream_t)stream, bits, clear != 0);
+}
+
+ams_status ams_device_copy(const void *d_src, void *d_dst, size_t bytes, void *stream) {
+  set_error("");
+  if (!bytes) return AMS_OK;
+  if (!d_src || !d_dst || (((uintptr_t)d_src | (uintptr_t)d_dst) & 15)) {
+    set_error("copy needs 16-byte aligned, non-NULL buffers");
+    return AMS_EINVAL;
+  }
+  return device_copy(d_src, d_dst, bytes, (hipStream_t)stream);
 }
 
 ams_status ams_workspace_stats(const void *d_ws, void *stream, ams_run_stats *out) {

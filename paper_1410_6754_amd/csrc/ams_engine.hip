@@ -92,6 +92,7 @@ struct Lev {
   uint32_t level, L, last, shrink;
   uint32_t rmax, b, a, mmax, Smax, TC, TB, HS, CH, rankG;
   uint32_t C, flags, Scap;
+  uint32_t capTile, capBlk, capSBlk;  // the level's table capacities
   uint64_t seed;
 };
 
@@ -291,7 +292,7 @@ __global__ void __launch_bounds__(1024) k_plan(Ws w, Lev lv) {
     // capacities are upper bounds by construction; if one were exceeded the
     // level processes nothing (and the overflow flag is raised) rather than
     // index past its tables
-    const bool over = tt > w.capTile || tb > w.capBlk || ts > w.capSBlk;
+    const bool over = tt > lv.capTile || tb > lv.capBlk || ts > lv.capSBlk;
     if (over) raise_error(w.ctr, 4u);
     w.ctr->lv_tiles[lv.level] = tt;
     w.ctr->P = over ? 0 : n;
@@ -2405,6 +2406,32 @@ __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint3
 }
 
 // ---------------------------------------------------------------------------
+// Plain streaming copy: the practical HBM ceiling the level passes are
+// measured against.  Each lane moves four 16-byte words per trip, all loads
+// issued before the stores.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_copy16(const v4u32 *src_, v4u32 *dst_, uint64_t n16) {
+  const GMem<v4u32> *src = (const GMem<v4u32> *)src_;
+  GMem<v4u32> *dst = (GMem<v4u32> *)dst_;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    v4u32 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = src[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) dst[i + u * stride] = v[u];
+  }
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+__global__ void k_copy_tail(const unsigned char *src, unsigned char *dst, uint64_t n) {
+  for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+ams_status device_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 static thread_local char g_err[512];
@@ -2519,6 +2546,24 @@ ams_status device_errors(hipStream_t s, uint32_t *bits, bool clear) {
 }
 
 size_t run_error_offset() { return offsetof(Ctr, overflow); }
+
+ams_status device_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
+  const uint64_t n16 = bytes / 16;
+  if (n16) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((n16 + 1023) / 1024, 4096);
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const v4u32 *)src, (v4u32 *)dst,
+                       n16);
+  }
+  if (bytes % 16)
+    hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, s, (const unsigned char *)src + n16 * 16,
+                       (unsigned char *)dst + n16 * 16, (uint64_t)(bytes % 16));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("kernel launch failed: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  return AMS_OK;
+}
 
 // Errors raised by the run whose counters sit at the start of ws (waits for s).
 ams_status run_errors(const void *ws, hipStream_t s, uint32_t *bits) {
@@ -2740,21 +2785,36 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     pl.o_act[l] = take(l < L ? (size_t)pl.lev[l].P * sizeof(Seg) : 0);
   pl.o_leaves = take((size_t)pl.capLeaf * sizeof(Seg));
   const bool any = L > 0;
+  // per-subproblem and per-tile tables: the kernels index them with the
+  // level's own strides, so each holds the largest level's rows
+  size_t eSamp = 0, eM = 0, eHist = 0, eBlk = 0, eTot = 0, eOff = 0, eCF = 0, eCS = 0, eCD = 0;
+  for (uint32_t l = 0; l < L; ++l) {
+    const LevelShape &ls = pl.lev[l];
+    eSamp = std::max(eSamp, (size_t)ls.P * ls.Smax);
+    eM = std::max(eM, (size_t)ls.P * ls.mmax);
+    eHist = std::max(eHist, (size_t)ls.tiles * ls.HS);
+    eBlk = std::max(eBlk, (size_t)ls.blocks * ls.HS);
+    eTot = std::max(eTot, (size_t)ls.P * ls.HS);
+    eOff = std::max(eOff, (size_t)ls.tiles * ls.CH);
+    eCF = std::max(eCF, (size_t)ls.P * 2 * (ls.CH + 1));
+    eCS = std::max(eCS, (size_t)ls.P * (ls.CH + 1));
+    eCD = std::max(eCD, (size_t)ls.P * ls.CH);
+  }
   pl.o_tileStart = take(any ? (size_t)(capAct + 1) * 4 : 0);
   pl.o_blkStart = take(any ? (size_t)(capAct + 1) * 4 : 0);
   pl.o_sampStart = take(any ? (size_t)(capAct + 1) * 4 : 0);
-  pl.o_samp = take(any ? (size_t)capAct * maxS * pl.kw : 0);
-  pl.o_spl = take(any ? (size_t)capAct * maxM * pl.kw : 0);
-  pl.o_tree = take(any ? (size_t)capAct * maxM * pl.kw : 0);
+  pl.o_samp = take(eSamp * pl.kw);
+  pl.o_spl = take(eM * pl.kw);
+  pl.o_tree = take(eM * pl.kw);
   pl.o_eq = take(any ? capAct : 0);
-  pl.o_hist = take(any ? (size_t)capTile * maxHS * 4 : 0);
-  pl.o_blkHist = take(any ? (size_t)capBlk * maxHS * 4 : 0);
-  pl.o_totals = take(any ? (size_t)capAct * maxHS * 4 : 0);
-  pl.o_tileOff = take(any ? (size_t)capTile * maxCH * 4 : 0);
-  pl.o_i2c = take(any ? (size_t)capAct * maxHS * 2 : 0);
-  pl.o_cfirst = take(any ? (size_t)capAct * 2 * (maxCH + 1) * 2 : 0);
-  pl.o_cstart = take(any ? (size_t)capAct * (maxCH + 1) * 4 : 0);
-  pl.o_cdst = take(any ? (size_t)capAct * maxCH : 0);
+  pl.o_hist = take(eHist * 4);
+  pl.o_blkHist = take(eBlk * 4);
+  pl.o_totals = take(eTot * 4);
+  pl.o_tileOff = take(eOff * 4);
+  pl.o_i2c = take(eTot * 2);
+  pl.o_cfirst = take(eCF * 2);
+  pl.o_cstart = take(eCS * 4);
+  pl.o_cdst = take(eCD);
   pl.o_nch = take(any ? (size_t)capAct * 4 : 0);
   pl.o_dbg = take((size_t)(nroots + 1) * 8);  // batch offsets upload / step outputs
   pl.bytes = o;
@@ -2820,6 +2880,9 @@ static LevTable lev_table(const Plan &pl, bool shrink_last) {
     v.C = pl.C;
     v.flags = pl.flags;
     v.Scap = 65536 / pl.kw;
+    v.capTile = ls.tiles;
+    v.capBlk = ls.blocks;
+    v.capSBlk = ls.sblocks;
     v.seed = pl.seed;
   }
   return lt;
