@@ -19,6 +19,9 @@ Contents
             grouping) and of the all-pairs-rank base case.
   checkers  independent output checks: sortedness, permutation, gather,
             stability, multiset fingerprint.
+  rlm       RLM-sort (Section 5): multisequence selection (Section 4.1),
+            the simultaneous selections of one level, and the whole
+            recurse-last multiway mergesort on small inputs.
 
 Every function cites the passage of the paper it follows.  Parity status of
 each function is listed in its docstring; the only function without a pin is
@@ -26,7 +29,7 @@ each function is listed in its docstring; the only function without a pin is
 is probabilistic).
 """
 
-from . import checkers, rng, steps  # noqa: F401
+from . import checkers, rlm, rng, steps  # noqa: F401
 from .sort import (  # noqa: F401
     KEY_F32,
     KEY_U32,
