@@ -137,6 +137,34 @@ ams_status ams_sort_pairs(ams_key_t t, const void *d_kin, const uint32_t *d_vin,
                           uint32_t *d_vout, size_t n, void *d_ws, size_t ws_bytes, void *stream,
                           const ams_params *p);
 
+/* ------------------------------------------------------------------------
+ * RLM-sort: recurse-last multiway mergesort (Section 5), the paper's second
+ * algorithm.  Every tile of tile_keys keys is sorted in LDS first (every PE
+ * sorts locally); then level by level every group of sorted sequences is
+ * split into `ways` parts of exactly equal size by multisequence selection
+ * (Section 4.1, all boundaries of a level side by side), each part receives
+ * its piece of every sequence and merges them, in slices of tile_keys keys,
+ * into the sorted sequences of the next level.  Parts of at most one tile
+ * are merged into the output.  The output is the same as ams_sort_keys'.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  uint32_t ways;       /* parts per group and level (0 = 16) */
+  uint32_t tile_keys;  /* keys per tile and per merged slice, multiple of 64, at most 4096
+                          (0 = 4096) */
+  uint64_t seed;       /* pivot seed (0 = fixed default); the output does not depend on it */
+  uint32_t flags;      /* AMS_FLAG_CHECK */
+  uint32_t reserved;
+} ams_rlm_params;
+
+/* Workspace of ams_rlm_sort_keys (0 on invalid arguments). */
+size_t ams_rlm_workspace_bytes(ams_key_t t, size_t n, const ams_rlm_params *p);
+
+/* RLM-sort of n keys (n <= AMS_MAX_SEGMENT); d_in and d_out may be the same
+ * buffer.  d_ws = NULL allocates the workspace in stream order.  Section 5;
+ * selection Section 4.1. */
+ams_status ams_rlm_sort_keys(ams_key_t t, const void *d_in, void *d_out, size_t n, void *d_ws,
+                             size_t ws_bytes, void *stream, const ams_rlm_params *p);
+
 /* Batched sort: segment i = elements [h_offsets[i], h_offsets[i+1]) of the
  * key (and optional payload) arrays is sorted independently, each result
  * identical to sorting that segment alone.  h_offsets (host, num+1 entries,
@@ -332,6 +360,17 @@ ams_status ams_step_level(ams_key_t t, const void *d_in, void *d_out, size_t n,
                           const void *d_splitters, uint32_t m, uint32_t r, uint32_t flags,
                           uint32_t *d_hist, uint32_t *d_children, uint32_t *n_children,
                           void *stream);
+
+/* Multisequence selection alone (Section 4.1), one RLM-sort level's
+ * boundaries: d_runs holds n keys (raw bits) that are sorted within
+ * consecutive runs of run_keys keys (the last run may be shorter); the
+ * keys are ordered by (ord value, run, position).  For j = 0..parts, row j
+ * of d_cuts (parts+1 rows of ceil(n / run_keys) uint32 entries, device)
+ * receives, for every run, how many of its keys are among the
+ * floor(j n / parts) smallest.  1 <= parts <= min(1024, n).  Synchronises
+ * `stream`; AMS_EDEVICE if a selection did not finish. */
+ams_status ams_step_multiselect(ams_key_t t, const void *d_runs, size_t n, uint32_t run_keys,
+                                uint32_t parts, uint64_t seed, uint32_t *d_cuts, void *stream);
 
 /* Bucket grouping alone (Section 6 and its lemma; Appendix C): w[0..nb)
  * weights -> d_out[0] = optimal maximum load L*, d_out[1] = number of groups

@@ -121,6 +121,17 @@ class RunStats(ctypes.Structure):
         return d
 
 
+class RlmParams(ctypes.Structure):
+    """Mirror of ams_rlm_params (0 = automatic)."""
+    _fields_ = [
+        ("ways", ctypes.c_uint32),
+        ("tile_keys", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
 # (name, restype, argtypes) of every exported symbol declared in include/ams.h
 _P = ctypes.c_void_p
 _U32 = ctypes.c_uint32
@@ -155,6 +166,9 @@ EXPORTS = [
     ("ams_workspace_stats", _I, [_P, _P, _P]),
     ("ams_server_inject_alloc_failures", _I, [_P, _U32]),
     ("ams_device_copy", _I, [_P, _P, _SZ, _P]),
+    ("ams_rlm_workspace_bytes", _SZ, [_I, _SZ, _P]),
+    ("ams_rlm_sort_keys", _I, [_I, _P, _P, _SZ, _P, _SZ, _P, _P]),
+    ("ams_step_multiselect", _I, [_I, _P, _SZ, _U32, _U32, _U64, _P, _P]),
 ]
 
 _lib = None

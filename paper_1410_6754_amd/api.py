@@ -230,7 +230,8 @@ __all__ = [
     "workspace_bytes", "batch_workspace_bytes", "alloc_workspace", "sort_keys", "sort_pairs",
     "sort_batch", "step_splitters", "step_level", "step_pack", "step_base_case", "_lib",
     "trace_start", "trace_stop", "autotune", "autotune_clear", "params_dict",
-    "device_errors", "workspace_stats",
+    "device_errors", "workspace_stats", "rlm_params", "rlm_workspace_bytes", "rlm_sort_keys",
+    "step_multiselect",
 ]
 
 
@@ -263,3 +264,45 @@ def workspace_stats(workspace: torch.Tensor, stream=None) -> dict:
     st = _lib.RunStats()
     check(lib().ams_workspace_stats(workspace.data_ptr(), _stream(stream), ctypes.byref(st)))
     return st.as_dict()
+
+
+def rlm_params(ways: int = 0, tile_keys: int = 0, seed: int = 0, flags: int = 0):
+    """ams_rlm_params (0 = automatic)."""
+    p = _lib.RlmParams()
+    p.ways, p.tile_keys, p.seed, p.flags = int(ways), int(tile_keys), int(seed), int(flags)
+    return p
+
+
+def rlm_workspace_bytes(key_type: int, n: int, params=None) -> int:
+    return int(lib().ams_rlm_workspace_bytes(key_type, n, _pref(params)))
+
+
+def rlm_sort_keys(keys: torch.Tensor, out: torch.Tensor | None = None, params=None,
+                  workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Sorted copy of ``keys`` by RLM-sort (recurse-last multiway mergesort)."""
+    kt = key_type_of(keys)
+    _dev(keys, "keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    _dev(out, "out")
+    if out.numel() != keys.numel() or out.dtype != keys.dtype:
+        raise ValueError("out must match keys")
+    ws = workspace.data_ptr() if workspace is not None else None
+    wsb = workspace.numel() if workspace is not None else 0
+    check(lib().ams_rlm_sort_keys(kt, keys.data_ptr(), out.data_ptr(), keys.numel(), ws, wsb,
+                                  _stream(stream), _pref(params)))
+    return out
+
+
+def step_multiselect(runs: torch.Tensor, run_keys: int, parts: int, seed: int = 0,
+                     stream=None) -> torch.Tensor:
+    """Cut table (parts+1, number of runs) of one RLM level over keys sorted
+    within consecutive runs of run_keys (synchronises)."""
+    kt = key_type_of(runs)
+    _dev(runs, "runs")
+    n = runs.numel()
+    S = (n + run_keys - 1) // run_keys
+    cuts = torch.empty((parts + 1, S), dtype=torch.uint32, device=runs.device)
+    check(lib().ams_step_multiselect(kt, runs.data_ptr(), n, run_keys, parts, seed,
+                                     cuts.data_ptr(), _stream(stream)))
+    return cuts

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libams.so")
 
-SOURCES = ["ams_engine.hip", "ams_tune.hip", "ams_api.cpp", "ams_server.cpp"]
+SOURCES = ["ams_engine.hip", "ams_rlm.hip", "ams_tune.hip", "ams_api.cpp", "ams_server.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "ams.h"
 #include "ams_device.h"
 
@@ -81,6 +83,28 @@ ams_status run_plan(const Plan &pl, void *ws, const RootSource &src, hipStream_t
                     const void *given_splitters);
 
 void set_error(const char *fmt, ...);
+
+// Kernel tracing: when ams_trace_start is on for the calling thread, a
+// TraceScope brackets the launches made in its lifetime with a pair of
+// events on the stream (name, or name.L<level>).
+struct TraceRec {
+  char name[32];
+  hipEvent_t e0, e1;
+};
+struct TraceScope {
+  TraceRec rec;
+  bool on;
+  hipStream_t s;
+  TraceScope(const char *name, uint32_t level, hipStream_t st);
+  ~TraceScope();
+};
+
+// RLM-sort's local sort: tiles of T keys of one array sorted in LDS by the
+// base case (ams_engine.hip); workspace of tile_sort_ws_bytes(n, T).
+size_t tile_sort_ws_bytes(uint64_t n, uint32_t T);
+ams_status run_tile_sort(int kt, bool pay, const void *in, const uint32_t *vin, void *out,
+                         uint32_t *vout, uint64_t n, uint32_t T, void *ws, hipStream_t s);
+uint32_t base_case_capacity(uint32_t kw, bool pay);
 
 // Parameters the autotuner chose for this shape class, if any (ams_tune.hip).
 bool tuned_lookup(int kt, bool pay, uint64_t total, uint64_t mx, uint64_t nroots,

@@ -2407,22 +2407,25 @@ __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint3
 
 // ---------------------------------------------------------------------------
 // Plain streaming copy: the practical HBM ceiling the level passes are
-// measured against.  Each lane moves four 16-byte words per trip, all loads
-// issued before the stores.
+// measured against.  Each workgroup copies one contiguous chunk, eight
+// 16-byte words per lane in flight (the fastest of the grid-stride and
+// chunked layouts measured on this GPU).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_copy16(const v4u32 *src_, v4u32 *dst_, uint64_t n16) {
+__global__ void __launch_bounds__(256) k_copy16(const v4u32 *src_, v4u32 *dst_, uint64_t n16,
+                                                uint64_t per) {
   const GMem<v4u32> *src = (const GMem<v4u32> *)src_;
   GMem<v4u32> *dst = (GMem<v4u32> *)dst_;
-  const uint64_t stride = (uint64_t)gridDim.x * 256;
-  uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  for (; i + 3 * stride < n16; i += 4 * stride) {
-    v4u32 v[4];
+  const uint64_t lo = (uint64_t)blockIdx.x * per;
+  const uint64_t hi = lo + per < n16 ? lo + per : n16;
+  uint64_t i = lo + threadIdx.x;
+  for (; i + 7 * 256 < hi; i += 8 * 256) {
+    v4u32 v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = src[i + u * stride];
+    for (int u = 0; u < 8; ++u) v[u] = src[i + u * 256];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) dst[i + u * stride] = v[u];
+    for (int u = 0; u < 8; ++u) dst[i + u * 256] = v[u];
   }
-  for (; i < n16; i += stride) dst[i] = src[i];
+  for (; i < hi; i += 256) dst[i] = src[i];
 }
 
 __global__ void k_copy_tail(const unsigned char *src, unsigned char *dst, uint64_t n) {
@@ -2449,32 +2452,24 @@ const char *last_error() { return g_err; }
 // Kernel tracing: when on, every launch of the calling thread is bracketed by
 // a pair of events on the launch stream; ams_trace_stop sums them per kernel.
 // ---------------------------------------------------------------------------
-struct TraceRec {
-  char name[32];
-  hipEvent_t e0, e1;
-};
-static thread_local bool g_trace_on = false;
-static thread_local std::vector<TraceRec> *g_trace = nullptr;
+thread_local bool g_trace_on = false;
+thread_local std::vector<TraceRec> *g_trace = nullptr;
 static thread_local std::vector<ams_trace_entry> *g_trace_acc = nullptr;
 
-struct TraceScope {
-  TraceRec rec;
-  bool on;
-  hipStream_t s;
-  TraceScope(const char *name, uint32_t level, hipStream_t st) : on(g_trace_on), s(st) {
-    if (!on) return;
-    if (level == 0xFFFFFFFFu) snprintf(rec.name, sizeof rec.name, "%s", name);
-    else snprintf(rec.name, sizeof rec.name, "%s.L%u", name, level);
-    (void)hipEventCreate(&rec.e0);
-    (void)hipEventCreate(&rec.e1);
-    (void)hipEventRecord(rec.e0, s);
-  }
-  ~TraceScope() {
-    if (!on) return;
-    (void)hipEventRecord(rec.e1, s);
-    g_trace->push_back(rec);
-  }
-};
+TraceScope::TraceScope(const char *name, uint32_t level, hipStream_t st) : on(g_trace_on), s(st) {
+  if (!on) return;
+  if (level == 0xFFFFFFFFu) snprintf(rec.name, sizeof rec.name, "%s", name);
+  else snprintf(rec.name, sizeof rec.name, "%s.L%u", name, level);
+  (void)hipEventCreate(&rec.e0);
+  (void)hipEventCreate(&rec.e1);
+  (void)hipEventRecord(rec.e0, s);
+}
+
+TraceScope::~TraceScope() {
+  if (!on) return;
+  (void)hipEventRecord(rec.e1, s);
+  g_trace->push_back(rec);
+}
 
 ams_status trace_start() {
   if (!g_trace) g_trace = new std::vector<TraceRec>();
@@ -2547,12 +2542,31 @@ ams_status device_errors(hipStream_t s, uint32_t *bits, bool clear) {
 
 size_t run_error_offset() { return offsetof(Ctr, overflow); }
 
+__global__ void k_fold_errors(const uint32_t *word) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && *word) atomicOr(&g_dev_errors, *word);
+}
+
+// ORs an error word that another kernel family keeps (RLM-sort's) into the
+// device's error word, in stream order.
+ams_status fold_device_errors(const uint32_t *d_word, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_errors, dim3(1), dim3(64), 0, s, d_word);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("kernel launch failed: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  return AMS_OK;
+}
+
 ams_status device_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
   const uint64_t n16 = bytes / 16;
   if (n16) {
-    const uint32_t grid = (uint32_t)std::min<uint64_t>((n16 + 1023) / 1024, 4096);
+    // chunks of 16 KiB (1024 words), at most 2^20 workgroups
+    uint64_t per = 1024;
+    while ((n16 + per - 1) / per > (1u << 20)) per *= 2;
+    const uint32_t grid = (uint32_t)((n16 + per - 1) / per);
     hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const v4u32 *)src, (v4u32 *)dst,
-                       n16);
+                       n16, per);
   }
   if (bytes % 16)
     hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, s, (const unsigned char *)src + n16 * 16,
@@ -3063,6 +3077,88 @@ ams_status run_plan(const Plan &pl, void *ws, const RootSource &src, hipStream_t
                     uint32_t *dbg_hist, uint32_t *dbg_children, uint32_t *dbg_nchild,
                     const void *given_splitters) {
   return run_plan_ex(pl, ws, src, s, dbg_hist, dbg_children, dbg_nchild, given_splitters, true);
+}
+
+// ---------------------------------------------------------------------------
+// Tile sort: consecutive tiles of T keys of one array (the last one ragged),
+// each sorted in LDS by the base case, written decoded to `out` (which may
+// be `in`: a tile is read whole before it is written).  RLM-sort's local
+// sort ("every PE sorts locally first", Section 5).
+// ---------------------------------------------------------------------------
+__global__ void k_tile_leaves(Ws w, uint64_t n, uint32_t T) {
+  const uint32_t nt = (uint32_t)((n + T - 1) / T);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt && i < w.capLeaf;
+       i += gridDim.x * blockDim.x) {
+    const uint64_t off = (uint64_t)i * T;
+    const uint32_t sz = (uint32_t)(n - off < T ? n - off : T);
+    w.leaves[i] = Seg{(uint32_t)off, sz, 0, make_meta(BUF_IN, LEAF_REG, 0, 0, 0)};
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) w.ctr->nleaf = nt < w.capLeaf ? nt : w.capLeaf;
+}
+
+uint32_t base_case_capacity(uint32_t kw, bool pay) { return fin_capacity(kw, pay); }
+
+size_t tile_sort_ws_bytes(uint64_t n, uint32_t T) {
+  const uint64_t nt = (n + T - 1) / T;
+  return align256(sizeof(Ctr)) + align256(sizeof(Root)) + align256(nt * sizeof(Seg));
+}
+
+template <int KT, bool PAY>
+static ams_status tile_sort_typed(const void *in, const uint32_t *vin, void *out, uint32_t *vout,
+                                  uint64_t n, uint32_t T, void *wsv, hipStream_t s) {
+  typedef typename Key<KT>::T K;
+  const uint32_t C = fin_capacity(sizeof(K), PAY);
+  if (T > C || T == 0) {
+    set_error("tile of %u keys exceeds the base case's %u", T, C);
+    return AMS_EINVAL;
+  }
+  char *base = (char *)wsv;
+  Ws w;
+  memset(&w, 0, sizeof w);
+  w.ctr = (Ctr *)base;
+  w.roots = (Root *)(base + align256(sizeof(Ctr)));
+  w.leaves = (Seg *)(base + align256(sizeof(Ctr)) + align256(sizeof(Root)));
+  w.nroots = 1;
+  const uint64_t nt = (n + T - 1) / T;
+  w.capLeaf = (uint32_t)nt;
+  Root R;
+  R.kin = in;
+  R.vin = vin;
+  R.kout = out;
+  R.vout = vout;
+  R.n = n;
+  R.tmp_off = 0;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w);
+  hipError_t e = hipMemcpyAsync(w.roots, &R, sizeof R, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    set_error("root upload: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  hipLaunchKernelGGL(k_tile_leaves, dim3((uint32_t)std::min<uint64_t>((nt + 255) / 256, 1024)),
+                     dim3(256), 0, s, w, n, T);
+  size_t ldsF = fin_smem_bytes<K, PAY>(C);
+  allow_lds(k_finish<KT, PAY>, ldsF);
+  {
+    TraceScope ts("tile_sort", 0xFFFFFFFFu, s);
+    hipLaunchKernelGGL((k_finish<KT, PAY>), dim3(grid_for(nt, PAY ? 256 : 512)),
+                       dim3(FIN_THREADS), ldsF, s, w, C, 32u, 14106754ull, 0u);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("kernel launch failed: %s", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  return AMS_OK;
+}
+
+ams_status run_tile_sort(int kt, bool pay, const void *in, const uint32_t *vin, void *out,
+                         uint32_t *vout, uint64_t n, uint32_t T, void *ws, hipStream_t s) {
+  if (kt == KT_U64) return pay ? tile_sort_typed<KT_U64, true>(in, vin, out, vout, n, T, ws, s)
+                               : tile_sort_typed<KT_U64, false>(in, vin, out, vout, n, T, ws, s);
+  if (kt == KT_U32) return pay ? tile_sort_typed<KT_U32, true>(in, vin, out, vout, n, T, ws, s)
+                               : tile_sort_typed<KT_U32, false>(in, vin, out, vout, n, T, ws, s);
+  return pay ? tile_sort_typed<KT_F32, true>(in, vin, out, vout, n, T, ws, s)
+             : tile_sort_typed<KT_F32, false>(in, vin, out, vout, n, T, ws, s);
 }
 
 // Step entry point helpers -------------------------------------------------
