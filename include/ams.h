@@ -130,6 +130,23 @@ size_t ams_batch_workspace_bytes(ams_key_t t, const uint64_t *h_offsets, size_t 
 ams_status ams_sort_keys(ams_key_t t, const void *d_in, void *d_out, size_t n, void *d_ws,
                          size_t ws_bytes, void *stream, const ams_params *p);
 
+/* Sort without allocating, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same sort as ams_sort_keys, with its workspace taken from
+ * a fixed array of AMS_NOALLOC_SCRATCH_BYTES in device memory that the
+ * library holds on every device it runs on until the process ends; the call
+ * makes no hipMalloc, hipFree or other allocating call.  `stream` must
+ * belong to the current device.  Returns AMS_EUNSUPPORTED when
+ * ams_workspace_bytes(t, n, 0, p) exceeds the array (about 4.5 M uint64 or
+ * 7.7 M 32-bit keys with the default parameters).  Every call on a device
+ * shares that device's array, which keeps the last call's contents (each
+ * call clears what it needs with its own kernels): calls that overlap on
+ * one device, from different streams or threads, race and must be
+ * serialised by the caller. */
+#define AMS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+ams_status ams_sort_keys_noalloc(ams_key_t t, const void *d_in, void *d_out, size_t n,
+                                 void *stream, const ams_params *p);
+
 /* Stable key/payload sort: payload d_vin[i] follows key d_kin[i].  Output
  * arrays may alias the inputs.  Section 6; stability from the position
  * tie-break of Section 2 / Appendix D. */

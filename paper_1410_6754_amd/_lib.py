@@ -169,6 +169,7 @@ EXPORTS = [
     ("ams_rlm_workspace_bytes", _SZ, [_I, _SZ, _P]),
     ("ams_rlm_sort_keys", _I, [_I, _P, _P, _SZ, _P, _SZ, _P, _P]),
     ("ams_step_multiselect", _I, [_I, _P, _SZ, _U32, _U32, _U64, _P, _P]),
+    ("ams_sort_keys_noalloc", _I, [_I, _P, _P, _SZ, _P, _P]),
 ]
 
 _lib = None

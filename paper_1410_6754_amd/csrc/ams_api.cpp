@@ -25,6 +25,7 @@ ams_status device_errors(hipStream_t s, uint32_t *bits, bool clear);
 ams_status run_errors(const void *ws, hipStream_t s, uint32_t *bits);
 ams_status run_stats(const void *ws, hipStream_t s, ams_run_stats *out);
 ams_status device_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+ams_status noalloc_scratch(void **ptr);
 }  // namespace ams
 
 using namespace ams;
@@ -175,6 +176,31 @@ size_t ams_batch_workspace_bytes(ams_key_t t, const uint64_t *h_offsets, size_t 
 ams_status ams_sort_keys(ams_key_t t, const void *d_in, void *d_out, size_t n, void *d_ws,
                          size_t ws_bytes, void *stream, const ams_params *p) {
   return sort_single(t, d_in, nullptr, d_out, nullptr, n, d_ws, ws_bytes, stream, p, false);
+}
+
+ams_status ams_sort_keys_noalloc(ams_key_t t, const void *d_in, void *d_out, size_t n,
+                                 void *stream, const ams_params *p) {
+  set_error("");
+  if (!valid_type(t)) {
+    set_error("unknown key type %d", (int)t);
+    return AMS_EINVAL;
+  }
+  if (n == 0) return AMS_OK;
+  Plan pl;
+  ams_status st = make_plan(pl, (int)t, false, nullptr, 1, n, p);
+  if (st) return st;
+  if (pl.bytes > NOALLOC_SCRATCH_BYTES) {
+    set_error("%zu keys need %zu bytes of workspace, more than the %zu-byte fixed array", n,
+              pl.bytes, (size_t)NOALLOC_SCRATCH_BYTES);
+    return AMS_EUNSUPPORTED;
+  }
+  void *ws = nullptr;
+  st = noalloc_scratch(&ws);
+  if (st) return st;
+  // the same path as ams_sort_keys with a caller workspace: nothing below
+  // allocates
+  return sort_single(t, d_in, nullptr, d_out, nullptr, n, ws, NOALLOC_SCRATCH_BYTES, stream, p,
+                     false);
 }
 
 ams_status ams_sort_pairs(ams_key_t t, const void *d_kin, const uint32_t *d_vin, void *d_kout,

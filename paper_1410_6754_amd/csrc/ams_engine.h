@@ -18,6 +18,9 @@ constexpr uint32_t MAXLEV = 4;         // partition levels at most
 constexpr uint32_t CMAX = 8192;        // keys one base-case workgroup sorts in LDS
 constexpr uint32_t FIN_THREADS = 512;  // base-case workgroup size
 constexpr uint32_t FMAX = 256;         // largest in-LDS fan-out of the base case
+// bytes of the fixed per-device workspace of ams_sort_keys_noalloc
+constexpr size_t NOALLOC_SCRATCH_BYTES = AMS_NOALLOC_SCRATCH_BYTES;
+constexpr uint32_t MAX_DEVICES = 64;
 // internal plan flag: the caller runs only level steps, never the base case
 constexpr uint32_t FLAG_NO_BASE_CASE = 1u << 31;
 

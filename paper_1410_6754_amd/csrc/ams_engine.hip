@@ -26,6 +26,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "ams_engine.h"
@@ -2435,6 +2436,14 @@ __global__ void k_copy_tail(const unsigned char *src, unsigned char *dst, uint64
 ams_status device_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Workspace of the no-allocation entry point: a fixed array that every GPU
+// the library runs on holds until the process ends.  Host code never uses
+// its name as an address (that is a host-side stand-in); the device address
+// comes from hipGetSymbolAddress, once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 static thread_local char g_err[512];
@@ -2555,6 +2564,31 @@ ams_status fold_device_errors(const uint32_t *d_word, hipStream_t s) {
     set_error("kernel launch failed: %s", hipGetErrorString(e));
     return AMS_EHIP;
   }
+  return AMS_OK;
+}
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device (with that device current) and kept.
+ams_status noalloc_scratch(void **ptr) {
+  static std::mutex mu;
+  static void *addr[MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= (int)MAX_DEVICES) {
+    set_error("no usable current device (%s)", hipGetErrorString(e));
+    return AMS_EHIP;
+  }
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+      return AMS_EHIP;
+    }
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
   return AMS_OK;
 }
 
