@@ -552,6 +552,7 @@ def bench_rlm(args) -> int:
         "config": {"workload": args.workload, "algorithm": "RLM-sort (Section 5)", "n": n,
                    "distribution": dist, "params": pkw},
         "roofline": roof, "passes": passes, "copy_ceiling": ceiling, "kernels": kernels,
+        "per_level_ms": {e["name"]: round(e["total_ms"] / e["launches"], 4) for e in trace},
         "cpu_baseline": None, "verified": verified,
     }
     print(json.dumps(line))

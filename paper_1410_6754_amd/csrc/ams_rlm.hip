@@ -35,6 +35,9 @@ ams_status fold_device_errors(const uint32_t *d_word, hipStream_t s);
 namespace {
 
 constexpr uint32_t RLM_NT = 256;        // selection threads (one sequence each)
+constexpr uint32_t RLM_M = 8;           // pivots per selection step
+constexpr uint32_t RLM_NONE = 0xFFu;    // "keep this end of the windows"
+constexpr uint32_t RLM_WAVE_SEQ = 256;  // groups of at most this many sequences: one wave per selection
 constexpr uint32_t RLM_MT = 512;        // merge threads
 constexpr uint32_t RLM_TMAX = 4096;     // largest tile (LDS of the merge)
 constexpr uint32_t RLM_MAXLEV = 16;
@@ -53,15 +56,18 @@ struct RGroup {
   uint32_t pad[2];
 };
 
-// One selection: the boundary in front of a part (j >= 1).
+// One selection: the boundary in front of a part (j >= 1).  Each step
+// draws up to RLM_M pivots from the remaining windows; the next step keeps
+// the windows between the two pivots whose ranks bracket the sought one.
 struct RSel {
-  uint64_t pivot;    // ord value of the pivot
-  uint32_t q, t;     // its sequence and position
-  uint32_t krem;     // rank still sought inside the windows (1-based)
-  uint32_t total;    // keys in the windows
-  uint32_t dir;      // decision to apply at the next step: 0 none, 1 left, 2 right
-  uint32_t done;     // 1: the windows' upper ends (after dir) are the cut
-  uint32_t arrive;   // blocks of the current step that have finished
+  uint64_t pv[RLM_M];            // pivots' ord values
+  uint32_t pq[RLM_M], pt[RLM_M]; // their sequences and positions
+  uint32_t np;                   // pivots of the current step
+  uint32_t krem;                 // rank still sought inside the windows (1-based)
+  uint32_t total;                // keys in the windows
+  uint32_t mlo, mhi;             // decision to apply: windows [cc[mlo], cc[mhi]) (RLM_NONE: keep)
+  uint32_t done;                 // 1: the windows' upper ends (after the decision) are the cut
+  uint32_t arrive;               // blocks of the current step that have finished
   uint32_t iter;
 };
 
@@ -86,27 +92,22 @@ struct RWs {
   RHdr *hdr;
   RGroup *groups, *children;
   RSel *sel;
-  uint32_t *lo, *hi, *cc, *cut, *bl, *br, *q;
-  uint32_t *scratch;  // per group: part counts (exscan space)
+  uint32_t *lo, *hi, *cut, *q;
+  uint32_t *cc;        // RLM_M rows of capCut: window keys before each pivot
+  uint32_t *bl;        // per selection block: RLM_M + 1 partial sums
+  uint32_t *blkOwner;  // selection block -> part
+  uint32_t *sliceOwner;  // merge slice -> part
+  uint32_t *sliceI0, *sliceI1;  // merge slice -> its first piece, one past its last
+  uint32_t capCut;
+  uint32_t *scratch;   // per group: part counts (exscan space)
 };
 
 AMS_DEV void rlm_error(const RWs &w, uint32_t bits) { atomicOr(&w.hdr->overflow, bits); }
 
-// A selection's state as another block of this launch may have left it.
-AMS_DEV RSel load_sel(const RSel *p) {
-  const volatile RSel *v = p;
-  RSel s;
-  s.pivot = v->pivot;
-  s.q = v->q;
-  s.t = v->t;
-  s.krem = v->krem;
-  s.total = v->total;
-  s.dir = v->dir;
-  s.done = v->done;
-  s.arrive = v->arrive;
-  s.iter = v->iter;
-  return s;
-}
+// A selection's control words as another block of this launch may have left
+// them (the pivots are read the same way, word by word).
+AMS_DEV uint32_t vload(const uint32_t *p) { return *(const volatile uint32_t *)p; }
+AMS_DEV uint64_t vload64(const uint64_t *p) { return *(const volatile uint64_t *)p; }
 
 AMS_DEV uint32_t seq_len(const RGroup &g, uint32_t i, uint32_t T) {
   const uint32_t a = i * T;
@@ -184,8 +185,124 @@ __global__ void __launch_bounds__(1024) k_rlm_children(RWs w, RLev lv) {
   }
 }
 
-// Windows of every selection: the whole of every sequence; the first pivot
-// drawn uniformly from the parent group.
+// Owner tables of a level: selection block -> part, merge slice -> part.
+__global__ void __launch_bounds__(RLM_NT) k_rlm_owners(RWs w, RLev lv) {
+  const uint32_t nc = w.hdr->nChildren;
+  for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+    const RGroup C = w.children[c];
+    const RGroup P = w.groups[C.parent];
+    const uint32_t S = (P.size + lv.T - 1) / lv.T;
+    const uint32_t nb = (S + RLM_NT - 1) / RLM_NT, ns = (C.size + lv.T - 1) / lv.T;
+    for (uint32_t k = threadIdx.x; k < nb; k += RLM_NT) w.blkOwner[C.blkBase + k] = c;
+    for (uint32_t k = threadIdx.x; k < ns; k += RLM_NT) w.sliceOwner[C.sliceBase + k] = c;
+  }
+}
+
+// Elements of x[lo, hi) (raw keys, sorted by their ord value) that precede
+// the pivot (ord value v, sequence q, position t) in the order (key,
+// sequence, position), for sequence i.
+template <int KT>
+AMS_DEV uint32_t count_before(const GMem<typename Key<KT>::T> *x, uint32_t lo, uint32_t hi,
+                              typename Key<KT>::T v, uint32_t i, uint32_t q, uint32_t t) {
+  typedef typename Key<KT>::T K;
+  if (i == q) return t < lo ? lo : (t > hi ? hi : t);
+  const bool le = i < q;  // earlier sequences: equal keys come first
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    const K y = Key<KT>::enc(x[mid]);
+    const bool before = le ? (y <= v) : (y < v);
+    if (before) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// count_before for every pivot of a step at once: all searches run over the
+// same window, so they advance in lock step (the window halves each round
+// whatever the comparisons give) and the loads of a round overlap.
+template <int KT>
+AMS_DEV void count_before_all(const GMem<typename Key<KT>::T> *x, uint32_t lo, uint32_t hi,
+                              const uint64_t *pv, const uint32_t *pq, const uint32_t *pt,
+                              uint32_t np, uint32_t i, uint32_t (&cnt)[RLM_M]) {
+  typedef typename Key<KT>::T K;
+  uint32_t base[RLM_M];
+  bool le[RLM_M];
+#pragma unroll
+  for (uint32_t m = 0; m < RLM_M; ++m) {
+    base[m] = lo;
+    le[m] = i < pq[m];  // earlier sequences: equal keys come first
+  }
+  uint32_t n = hi - lo;
+  if (n) {
+    // invariant: the count lies in [base, base + n]
+    while (n > 1) {
+      const uint32_t half = n >> 1;
+      K y[RLM_M];
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) y[m] = Key<KT>::enc(x[base[m] + half - 1]);
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) {
+        const K v = (K)pv[m];
+        const bool before = le[m] ? (y[m] <= v) : (y[m] < v);
+        base[m] += before ? half : 0u;
+      }
+      n -= half;
+    }
+    K y[RLM_M];
+#pragma unroll
+    for (uint32_t m = 0; m < RLM_M; ++m) y[m] = Key<KT>::enc(x[base[m]]);
+#pragma unroll
+    for (uint32_t m = 0; m < RLM_M; ++m) {
+      const K v = (K)pv[m];
+      const bool before = le[m] ? (y[m] <= v) : (y[m] < v);
+      base[m] += before ? 1u : 0u;
+    }
+  }
+#pragma unroll
+  for (uint32_t m = 0; m < RLM_M; ++m) {
+    uint32_t c = base[m];
+    if (i == pq[m]) c = pt[m] < lo ? lo : (pt[m] > hi ? hi : pt[m]);  // the pivot's own sequence
+    cnt[m] = m < np ? c : lo;
+  }
+}
+
+// The decision of a step from the pivots' left counts: the windows between
+// the pivot of largest rank below the sought one and the pivot of smallest
+// rank at or above it.  Returns the new (mlo, mhi, krem, total, done).
+struct RDecision {
+  uint32_t mlo, mhi, krem, total, done;
+};
+AMS_DEV RDecision decide(const uint32_t *left, uint32_t np, uint32_t krem, uint32_t total) {
+  uint32_t mlo = RLM_NONE, mhi = RLM_NONE, vlo = 0, vhi = total;
+  for (uint32_t m = 0; m < np; ++m) {
+    const uint32_t v = left[m];
+    if (v >= krem) {
+      if (v < vhi || mhi == RLM_NONE) {
+        vhi = v;
+        mhi = m;
+      }
+    } else if (v >= vlo) {
+      vlo = v;
+      mlo = m;
+    }
+  }
+  RDecision d;
+  d.mlo = mlo;
+  d.mhi = mhi;
+  d.krem = krem - vlo;
+  d.total = vhi - vlo;
+  d.done = d.total == d.krem;
+  return d;
+}
+
+// Pivot stream of a selection: draw m of step `iter`.
+AMS_DEV uint32_t pivot_draw(const RLev &lv, uint32_t c, uint32_t iter, uint32_t m,
+                            uint32_t total) {
+  const uint64_t st = stream_state(lv.seed, RLM_STREAM + lv.level, c, iter);
+  return draw_pos(st, m, total);
+}
+
+// Windows of every selection: the whole of every sequence; the first pivots
+// drawn uniformly from the parent group (whose sequences are consecutive).
 template <int KT>
 __global__ void __launch_bounds__(RLM_NT) k_rlm_sel_init(RWs w, RLev lv, const void *src_) {
   typedef typename Key<KT>::T K;
@@ -198,196 +315,357 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_sel_init(RWs w, RLev lv, const v
     for (uint32_t i = threadIdx.x; i < S; i += RLM_NT) {
       w.lo[C.cutBase + i] = 0;
       w.hi[C.cutBase + i] = seq_len(P, i, lv.T);
-      w.cc[C.cutBase + i] = 0;
     }
-    if (threadIdx.x == 0) {
-      RSel s;
-      memset(&s, 0, sizeof s);
-      s.krem = C.rank;
-      s.total = P.size;
-      s.done = C.j == 0 ? 1u : 0u;  // the first part starts at rank 0: nothing to select
-      if (!s.done) {
-        const uint64_t st = stream_state(lv.seed, RLM_STREAM + lv.level, c, 0);
-        const uint32_t u = draw_pos(st, 0, P.size);
-        s.q = u / lv.T;
-        s.t = u - s.q * lv.T;
-        s.pivot = (uint64_t)Key<KT>::enc(src[P.start + u]);
+    if (threadIdx.x < RLM_M) {
+      const uint32_t m = threadIdx.x;
+      RSel *sp = w.sel + c;
+      const uint32_t np = P.size < RLM_M ? P.size : RLM_M;
+      if (m < np && C.j != 0) {
+        const uint32_t u = pivot_draw(lv, c, 0, m, P.size);
+        sp->pq[m] = u / lv.T;
+        sp->pt[m] = u % lv.T;
+        sp->pv[m] = (uint64_t)Key<KT>::enc(src[P.start + u]);
       }
-      w.sel[c] = s;
+      if (m == 0) {
+        sp->np = np;
+        sp->krem = C.rank;
+        sp->total = P.size;
+        sp->mlo = RLM_NONE;
+        sp->mhi = RLM_NONE;
+        sp->done = C.j == 0 ? 1u : 0u;  // the first part starts at rank 0
+        sp->arrive = 0;
+        sp->iter = 0;
+      }
     }
   }
 }
 
-// Elements of x[lo, hi) (raw keys, sorted by their ord value) that precede
-// the pivot (ord value v, sequence q, position t) in the order (key,
-// sequence, position), for sequence i.
+// Applies the previous decision to sequence i's window and counts the
+// window keys before each pivot of the step; returns the window.
 template <int KT>
-AMS_DEV uint32_t count_before(const GMem<typename Key<KT>::T> *x, uint32_t lo, uint32_t hi,
-                              typename Key<KT>::T v, uint32_t i, uint32_t q, uint32_t t) {
+AMS_DEV void sel_entry(const RWs &w, const RGroup &P, uint32_t e, uint32_t i, uint32_t T,
+                       uint32_t mlo, uint32_t mhi, uint32_t np, const uint64_t *pv,
+                       const uint32_t *pq, const uint32_t *pt, const GMem<typename Key<KT>::T> *src,
+                       uint32_t (&L)[RLM_M], uint32_t &W) {
   typedef typename Key<KT>::T K;
-  if (i == q) return t;
-  const bool le = i < q;  // earlier sequences: equal keys come first
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    const K y = Key<KT>::enc(x[mid]);
-    const bool before = le ? (y <= v) : (y < v);
-    if (before) lo = mid + 1; else hi = mid;
+  uint32_t lo = w.lo[e], hi = w.hi[e];
+  if (mlo != RLM_NONE) lo = w.cc[(size_t)mlo * w.capCut + e];
+  if (mhi != RLM_NONE) hi = w.cc[(size_t)mhi * w.capCut + e];
+  w.lo[e] = lo;
+  w.hi[e] = hi;
+  const GMem<K> *x = src + P.start + (size_t)i * T;
+  uint32_t cnt[RLM_M];
+  count_before_all<KT>(x, lo, hi, pv, pq, pt, np, i, cnt);
+#pragma unroll
+  for (uint32_t m = 0; m < RLM_M; ++m) {
+    if (m < np) w.cc[(size_t)m * w.capCut + e] = cnt[m];
+    L[m] = cnt[m] - lo;
   }
-  return lo;
+  W = hi - lo;
 }
 
-// One step of every unfinished selection; each item is (selection, block of
-// RLM_NT sequences).  The last block of a selection to finish its step
-// decides the side and draws the next pivot.  A selection with a single
-// block runs its steps back to back inside the launch (at most lv.itmax).
+// Small groups (at most RLM_WAVE_SEQ sequences): one wavefront runs a whole
+// selection, steps back to back (at most lv.itmax), up to four sequences
+// per lane.
 template <int KT>
-__global__ void __launch_bounds__(RLM_NT) k_rlm_select(RWs w, RLev lv, const void *src_) {
+__global__ void __launch_bounds__(RLM_NT) k_rlm_select_wave(RWs w, RLev lv, const void *src_) {
   typedef typename Key<KT>::T K;
   const GMem<K> *src = (const GMem<K> *)src_;
-  __shared__ uint32_t red[2 * RLM_NT / 64];
-  __shared__ uint32_t sh[4];
-  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-  const uint32_t nc = w.hdr->nChildren, nb = w.hdr->cnt[1];
-  for (uint32_t item = blockIdx.x; item < nb; item += gridDim.x) {
-    // owner: the last child whose first block is <= item
-    uint32_t lo_c = 0, hi_c = nc;
-    while (hi_c - lo_c > 1) {
-      const uint32_t mid = (lo_c + hi_c) >> 1;
-      if (w.children[mid].blkBase <= item) lo_c = mid; else hi_c = mid;
-    }
-    const uint32_t c = lo_c;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t nc = w.hdr->nChildren;
+  const uint32_t waves = gridDim.x * (RLM_NT / 64);
+  for (uint32_t c = blockIdx.x * (RLM_NT / 64) + (threadIdx.x >> 6); c < nc; c += waves) {
     const RGroup C = w.children[c];
     const RGroup P = w.groups[C.parent];
     const uint32_t S = (P.size + lv.T - 1) / lv.T;
-    const uint32_t nblk = (S + RLM_NT - 1) / RLM_NT;
-    const uint32_t b = item - C.blkBase;
-    const uint32_t rounds = nblk == 1 ? lv.itmax : 1u;
-    for (uint32_t round = 0; round < rounds; ++round) {
-      const RSel s = load_sel(w.sel + c);
-      if (s.done) break;
-      const uint32_t i = b * RLM_NT + tid;
-      uint32_t L = 0, R = 0;
-      if (i < S) {
-        const uint32_t e = C.cutBase + i;
-        uint32_t lo = w.lo[e], hi = w.hi[e];
-        const uint32_t prev = w.cc[e];
-        if (s.dir == 1) hi = prev;
-        else if (s.dir == 2) lo = prev;
-        const uint32_t cnt = count_before<KT>(src + P.start + (size_t)i * lv.T, lo, hi,
-                                              (K)s.pivot, i, s.q, s.t);
-        w.lo[e] = lo;
-        w.hi[e] = hi;
-        w.cc[e] = cnt;
-        L = cnt - lo;
-        R = hi - cnt;
-      }
-      L = wave_sum(L);
-      R = wave_sum(R);
-      if (lane == 0) {
-        red[wave] = L;
-        red[RLM_NT / 64 + wave] = R;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        uint32_t bl = 0, br = 0;
-        for (uint32_t q = 0; q < RLM_NT / 64; ++q) {
-          bl += red[q];
-          br += red[RLM_NT / 64 + q];
+    if (S > RLM_WAVE_SEQ) continue;  // the block kernel's
+    RSel *sp = w.sel + c;
+    uint32_t np = sp->np, krem = sp->krem, total = sp->total, mlo = sp->mlo, mhi = sp->mhi;
+    uint32_t done = sp->done, iter = sp->iter;
+    uint64_t pv[RLM_M];
+    uint32_t pq[RLM_M], pt[RLM_M];
+#pragma unroll
+    for (uint32_t m = 0; m < RLM_M; ++m) {
+      pv[m] = sp->pv[m];
+      pq[m] = sp->pq[m];
+      pt[m] = sp->pt[m];
+    }
+    for (uint32_t step = 0; step < lv.itmax && !done; ++step) {
+      uint32_t Lsum[RLM_M];
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) Lsum[m] = 0;
+      for (uint32_t k = 0; k < RLM_WAVE_SEQ / 64; ++k) {
+        const uint32_t i = k * 64 + lane;
+        if (i < S) {
+          uint32_t L[RLM_M], Wi;
+          sel_entry<KT>(w, P, C.cutBase + i, i, lv.T, mlo, mhi, np, pv, pq, pt, src, L, Wi);
+#pragma unroll
+          for (uint32_t m = 0; m < RLM_M; ++m) Lsum[m] += L[m];
         }
-        w.bl[C.blkBase + b] = bl;
-        w.br[C.blkBase + b] = br;
-        __threadfence();
-        const uint32_t old = atomicAdd(&w.sel[c].arrive, 1u);
-        sh[0] = old + 1 == nblk ? 1u : 0u;
       }
-      __syncthreads();
-      if (!sh[0]) break;  // another block finishes this step
-      __threadfence();
-      // --- last block of the step: decide, then draw the next pivot ------
-      uint32_t left = 0;
-      for (uint32_t q = tid; q < nblk; q += RLM_NT) left += ((volatile uint32_t *)w.bl)[C.blkBase + q];
-      left = wave_sum(left);
-      __syncthreads();
-      if (lane == 0) red[wave] = left;
-      __syncthreads();
-      left = 0;
-      for (uint32_t q = 0; q < RLM_NT / 64; ++q) left += red[q];
-      uint32_t krem = s.krem, total, dir;
-      if (left >= krem) {
-        dir = 1;
-        total = left;
-      } else {
-        dir = 2;
-        krem -= left;
-        total = s.total - left;
-      }
-      RSel ns = s;
-      ns.dir = dir;
-      ns.krem = krem;
-      ns.total = total;
-      ns.arrive = 0;
-      ns.iter = s.iter + 1;
-      if (total == krem) {
-        ns.done = 1;
-      } else {
-        // u-th key (0-based) of the new windows, in sequence order
-        const uint64_t st = stream_state(lv.seed, RLM_STREAM + lv.level, c, ns.iter);
-        uint32_t u = draw_pos(st, 0, total);
-        const uint32_t *part = dir == 1 ? w.bl : w.br;
-        // block holding it: a sequential walk over the block totals (at
-        // most a few hundred)
-        uint32_t bsel = 0;
-        if (tid == 0) {
-          uint32_t acc = 0;
-          for (bsel = 0; bsel < nblk; ++bsel) {
-            const uint32_t v = ((volatile uint32_t *)part)[C.blkBase + bsel];
-            if (u < acc + v) break;
-            acc += v;
-          }
-          sh[1] = bsel < nblk ? bsel : nblk - 1;
-          sh[2] = u - acc;
-        }
-        __syncthreads();
-        bsel = sh[1];
-        u = sh[2];
-        // sequence holding it inside that block
-        const uint32_t i = bsel * RLM_NT + tid;
-        uint32_t wlo = 0, wsz = 0;
+      uint32_t left[RLM_M];
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) left[m] = wave_sum(Lsum[m]);
+      const RDecision d = decide(left, np, krem, total);
+      mlo = d.mlo;
+      mhi = d.mhi;
+      krem = d.krem;
+      total = d.total;
+      done = d.done;
+      ++iter;
+      if (done) break;
+      // next pivots: draw m is the u-th key of the new windows in sequence
+      // order; each lane holds four sequences' window sizes
+      uint32_t wlo[RLM_WAVE_SEQ / 64], wsz[RLM_WAVE_SEQ / 64], lsum = 0;
+      for (uint32_t k = 0; k < RLM_WAVE_SEQ / 64; ++k) {
+        const uint32_t i = lane * (RLM_WAVE_SEQ / 64) + k;  // lane-major for the scan
+        uint32_t a = 0, b = 0;
         if (i < S) {
           const uint32_t e = C.cutBase + i;
-          const uint32_t lo = ((volatile uint32_t *)w.lo)[e], hi = ((volatile uint32_t *)w.hi)[e];
-          const uint32_t cc = ((volatile uint32_t *)w.cc)[e];
-          wlo = dir == 1 ? lo : cc;
-          wsz = dir == 1 ? cc - lo : hi - cc;
+          a = mlo == RLM_NONE ? w.lo[e] : w.cc[(size_t)mlo * w.capCut + e];
+          b = mhi == RLM_NONE ? w.hi[e] : w.cc[(size_t)mhi * w.capCut + e];
         }
-        const uint32_t incl = wave_incl_scan(wsz);
-        if (lane == 63) red[wave] = incl;
-        __syncthreads();
-        uint32_t off = 0;
-        for (uint32_t q = 0; q < wave; ++q) off += red[q];
-        const uint32_t first = off + incl - wsz;
-        if (tid == 0) sh[3] = 0xFFFFFFFFu;
-        __syncthreads();
-        if (wsz && u >= first && u < first + wsz) {
-          sh[3] = i;
-          sh[1] = wlo + (u - first);
-        }
-        __syncthreads();
-        if (sh[3] == 0xFFFFFFFFu) {  // cannot happen: the partials cover u
-          ns.done = 1;
-          if (tid == 0) rlm_error(w, AMS_DEVERR_RANGE);
-        } else {
-          ns.q = sh[3];
-          ns.t = sh[1];
-          ns.pivot = (uint64_t)Key<KT>::enc(src[P.start + (size_t)ns.q * lv.T + ns.t]);
-        }
+        wlo[k] = a;
+        wsz[k] = b - a;
+        lsum += b - a;
       }
-      if (tid == 0) {
-        w.sel[c] = ns;
-        __threadfence();
+      const uint32_t incl = wave_incl_scan(lsum);
+      np = total < RLM_M ? total : RLM_M;
+      // the draws: the lane whose sequences hold key u of the windows finds
+      // the sequence and position and loads the pivot; all draws at once
+      uint32_t myq[RLM_M], myt[RLM_M];
+      uint64_t myv[RLM_M];
+      bool own[RLM_M];
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) {
+        const uint32_t u = m < np ? pivot_draw(lv, c, iter, m, total) : 0xFFFFFFFFu;
+        own[m] = u >= incl - lsum && u < incl;
+        uint32_t r = u - (incl - lsum), q = 0, t = 0;
+        bool found = false;
+#pragma unroll
+        for (uint32_t k = 0; k < RLM_WAVE_SEQ / 64; ++k) {
+          const bool here = own[m] && !found && r < wsz[k];
+          q = here ? lane * (RLM_WAVE_SEQ / 64) + k : q;
+          t = here ? wlo[k] + r : t;
+          r -= (own[m] && !found && !here) ? wsz[k] : 0u;
+          found = found || here;
+        }
+        own[m] = own[m] && found;
+        myq[m] = q;
+        myt[m] = t;
+        myv[m] = own[m] ? (uint64_t)Key<KT>::enc(src[P.start + (size_t)q * lv.T + t]) : 0ull;
+      }
+      uint32_t got = np;
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) {
+        if (m >= np) break;
+        const uint64_t owner = ballot(own[m]);
+        if (!owner) {  // cannot happen: the window sizes cover u
+          got = m < got ? m : got;
+          continue;
+        }
+        const uint32_t sl = (uint32_t)__builtin_ctzll(owner);
+        pq[m] = __shfl(myq[m], sl, 64);
+        pt[m] = __shfl(myt[m], sl, 64);
+        pv[m] = __shfl(myv[m], sl, 64);
+      }
+      if (got < np) {
+        if (lane == 0) rlm_error(w, AMS_DEVERR_RANGE);
+        np = got;
+      }
+    }
+    if (lane == 0) {
+      sp->np = np;
+      sp->krem = krem;
+      sp->total = total;
+      sp->mlo = mlo;
+      sp->mhi = mhi;
+      sp->done = done;
+      sp->iter = iter;
+    }
+  }
+}
+
+// Large groups: one step of every unfinished selection per launch; an item
+// is (selection, block of RLM_NT sequences).  The last block of a selection
+// to finish the step decides and draws the next pivots.
+template <int KT>
+__global__ void __launch_bounds__(RLM_NT) k_rlm_select_blocks(RWs w, RLev lv, const void *src_) {
+  typedef typename Key<KT>::T K;
+  const GMem<K> *src = (const GMem<K> *)src_;
+  constexpr uint32_t NW = RLM_NT / 64;
+  constexpr uint32_t PB = RLM_M + 1;  // partials per block
+  __shared__ uint32_t red[PB * NW];
+  __shared__ uint32_t sh[8];
+  __shared__ uint32_t sleft[RLM_M];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint32_t nb = w.hdr->cnt[1];
+  for (uint32_t item = blockIdx.x; item < nb; item += gridDim.x) {
+    const uint32_t c = w.blkOwner[item];
+    const RGroup C = w.children[c];
+    const RGroup P = w.groups[C.parent];
+    const uint32_t S = (P.size + lv.T - 1) / lv.T;
+    if (S <= RLM_WAVE_SEQ) continue;  // the wave kernel's
+    RSel *sp = w.sel + c;
+    if (vload(&sp->done)) continue;
+    const uint32_t nblk = (S + RLM_NT - 1) / RLM_NT;
+    const uint32_t b = item - C.blkBase;
+    const uint32_t np = sp->np, mlo = sp->mlo, mhi = sp->mhi;
+    uint64_t pv[RLM_M];
+    uint32_t pq[RLM_M], pt[RLM_M];
+#pragma unroll
+    for (uint32_t m = 0; m < RLM_M; ++m) {
+      pv[m] = sp->pv[m];
+      pq[m] = sp->pq[m];
+      pt[m] = sp->pt[m];
+    }
+    uint32_t L[RLM_M], Wi = 0;
+#pragma unroll
+    for (uint32_t m = 0; m < RLM_M; ++m) L[m] = 0;
+    const uint32_t i = b * RLM_NT + tid;
+    if (i < S) sel_entry<KT>(w, P, C.cutBase + i, i, lv.T, mlo, mhi, np, pv, pq, pt, src, L, Wi);
+#pragma unroll
+    for (uint32_t m = 0; m < RLM_M; ++m) L[m] = wave_sum(L[m]);
+    Wi = wave_sum(Wi);
+    if (lane == 0) {
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) red[m * NW + wave] = L[m];
+      red[RLM_M * NW + wave] = Wi;
+    }
+    __syncthreads();
+    if (tid < PB) {
+      uint32_t v = 0;
+      for (uint32_t q = 0; q < NW; ++q) v += red[tid * NW + q];
+      w.bl[(size_t)(C.blkBase + b) * PB + tid] = v;
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) sh[0] = atomicAdd(&sp->arrive, 1u) + 1 == nblk ? 1u : 0u;
+    __syncthreads();
+    if (!sh[0]) continue;  // another block finishes this step
+    __threadfence();
+    // --- last block of the step: sum the partials and decide -------------
+    // (plain loads: the fence after the arrival count orders them after the
+    // other blocks' writes)
+    const uint32_t *blp = w.bl + (size_t)C.blkBase * PB;
+    {
+      uint32_t acc[RLM_M];
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) acc[m] = 0;
+      for (uint32_t q = tid; q < nblk; q += RLM_NT) {
+#pragma unroll
+        for (uint32_t m = 0; m < RLM_M; ++m) acc[m] += blp[(size_t)q * PB + m];
+      }
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) acc[m] = wave_sum(acc[m]);
+      __syncthreads();
+      if (lane == 0) {
+#pragma unroll
+        for (uint32_t m = 0; m < RLM_M; ++m) red[m * NW + wave] = acc[m];
+      }
+      __syncthreads();
+      if (tid < RLM_M) {
+        uint32_t v = 0;
+        for (uint32_t q = 0; q < NW; ++q) v += red[tid * NW + q];
+        sleft[tid] = v;
       }
       __syncthreads();
     }
+    const RDecision d = decide(sleft, np, sp->krem, sp->total);
+    const uint32_t iter = sp->iter + 1;
+    const uint32_t np2 = d.total < RLM_M ? d.total : RLM_M;
+    if (!d.done) {
+      // level 1: per-block sizes of the new windows over contiguous chunks
+      // of blocks per thread, scanned; the thread whose chunk holds draw m
+      // finds its block and the rank inside it
+      const uint32_t per = (nblk + RLM_NT - 1) / RLM_NT;
+      const uint32_t q0 = tid * per < nblk ? tid * per : nblk;
+      const uint32_t q1 = q0 + per < nblk ? q0 + per : nblk;
+      auto bsize = [&](uint32_t q) -> uint32_t {
+        const uint32_t *r = blp + (size_t)q * PB;
+        const uint32_t hiv = d.mhi == RLM_NONE ? r[RLM_M] : r[d.mhi];
+        const uint32_t lov = d.mlo == RLM_NONE ? 0u : r[d.mlo];
+        return hiv - lov;
+      };
+      uint32_t mine = 0;
+      for (uint32_t q = q0; q < q1; ++q) mine += bsize(q);
+      const uint32_t incl = wave_incl_scan(mine);
+      if (lane == 63) red[wave] = incl;
+      __syncthreads();
+      uint32_t off = 0;
+      for (uint32_t q = 0; q < wave; ++q) off += red[q];
+      const uint32_t first = off + incl - mine;
+      __shared__ uint32_t sbq[RLM_M], srr[RLM_M];
+      if (tid < RLM_M) sbq[tid] = 0xFFFFFFFFu;
+      __syncthreads();
+      for (uint32_t m = 0; m < np2; ++m) {
+        const uint32_t u = pivot_draw(lv, c, iter, m, d.total);
+        if (mine && u >= first && u < first + mine) {
+          uint32_t r = u - first, q = q0;
+          for (; q < q1; ++q) {
+            const uint32_t z = bsize(q);
+            if (r < z) break;
+            r -= z;
+          }
+          sbq[m] = q;
+          srr[m] = r;
+        }
+      }
+      __syncthreads();
+      // level 2: inside each draw's block, the sequence holding its rank
+      uint32_t za[RLM_M], zs[RLM_M];
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) {
+        const uint32_t bq = m < np2 && sbq[m] < nblk ? sbq[m] : 0xFFFFFFFFu;
+        const uint32_t ii = bq == 0xFFFFFFFFu ? S : bq * RLM_NT + tid;
+        za[m] = 0;
+        zs[m] = 0;
+        if (ii < S) {
+          const uint32_t e = C.cutBase + ii;
+          const uint32_t lo_ = d.mlo == RLM_NONE ? w.lo[e] : w.cc[(size_t)d.mlo * w.capCut + e];
+          const uint32_t hi_ = d.mhi == RLM_NONE ? w.hi[e] : w.cc[(size_t)d.mhi * w.capCut + e];
+          za[m] = lo_;
+          zs[m] = hi_ - lo_;
+        }
+      }
+      uint32_t inc2[RLM_M];
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) inc2[m] = wave_incl_scan(zs[m]);
+      __syncthreads();
+      if (lane == 63) {
+#pragma unroll
+        for (uint32_t m = 0; m < RLM_M; ++m) red[m * NW + wave] = inc2[m];
+      }
+      __syncthreads();
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) {
+        if (m >= np2 || sbq[m] >= nblk) continue;
+        uint32_t off2 = 0;
+        for (uint32_t q = 0; q < wave; ++q) off2 += red[m * NW + q];
+        const uint32_t f2 = off2 + inc2[m] - zs[m];
+        const uint32_t rr = srr[m];
+        if (zs[m] && rr >= f2 && rr < f2 + zs[m]) {
+          const uint32_t ii = sbq[m] * RLM_NT + tid;
+          const uint32_t t = za[m] + (rr - f2);
+          sp->pq[m] = ii;
+          sp->pt[m] = t;
+          sp->pv[m] = (uint64_t)Key<KT>::enc(src[P.start + (size_t)ii * lv.T + t]);
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      sp->np = np2;
+      sp->krem = d.krem;
+      sp->total = d.total;
+      sp->mlo = d.mlo;
+      sp->mhi = d.mhi;
+      sp->done = d.done;
+      sp->iter = iter;
+      sp->arrive = 0;
+      __threadfence();
+    }
+    __syncthreads();
   }
 }
 
@@ -398,13 +676,14 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_cut(RWs w, RLev lv) {
     const RGroup C = w.children[c];
     const RGroup P = w.groups[C.parent];
     const uint32_t S = (P.size + lv.T - 1) / lv.T;
-    const RSel s = w.sel[c];
-    if (threadIdx.x == 0 && !s.done) rlm_error(w, AMS_DEVERR_RANGE);
+    const RSel *sp = w.sel + c;
+    const uint32_t done = sp->done, mhi = sp->mhi;
+    if (threadIdx.x == 0 && !done) rlm_error(w, AMS_DEVERR_RANGE);
     for (uint32_t i = threadIdx.x; i < S; i += RLM_NT) {
       const uint32_t e = C.cutBase + i;
       uint32_t v;
       if (C.j == 0) v = 0;
-      else v = s.dir == 1 ? w.cc[e] : w.hi[e];
+      else v = mhi == RLM_NONE ? w.hi[e] : w.cc[(size_t)mhi * w.capCut + e];
       w.cut[e] = v;
     }
   }
@@ -431,6 +710,23 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_pieces(RWs w, RLev lv) {
       Q[S] = tot;
       if (tot != C.size) rlm_error(w, AMS_DEVERR_RANGE);
     }
+    __syncthreads();
+    if (tot != C.size) continue;
+    // the pieces each slice of T keys overlaps: slice k starts in the piece
+    // holding key k*T and ends in the piece holding its last key
+    const uint32_t nsl = (C.size + lv.T - 1) / lv.T;
+    for (uint32_t i = threadIdx.x; i < S; i += RLM_NT) {
+      const uint32_t qa = Q[i], qb = Q[i + 1];
+      if (qa >= qb) continue;  // empty piece
+      for (uint32_t k = (qa + lv.T - 1) / lv.T; k < nsl && k * lv.T < qb; ++k)
+        w.sliceI0[C.sliceBase + k] = i;
+      const uint32_t k0 = qa / lv.T;  // slices whose last key may lie in [qa, qb)
+      for (uint32_t k = k0; k < nsl; ++k) {
+        const uint32_t lastKey = ((k + 1) * lv.T < C.size ? (k + 1) * lv.T : C.size) - 1;
+        if (lastKey >= qb) break;
+        if (lastKey >= qa) w.sliceI1[C.sliceBase + k] = i + 1;
+      }
+    }
   }
 }
 
@@ -450,27 +746,25 @@ AMS_DEV uint32_t upper_le(const uint32_t *v, uint32_t n, uint32_t x) {
 }
 
 template <int KT>
-__global__ void __launch_bounds__(RLM_MT) k_rlm_merge(RWs w, RLev lv, const void *src_,
-                                                      void *dst_) {
+__global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const void *src_,
+                                                         void *dst_) {
   typedef typename Key<KT>::T K;
+  constexpr uint32_t PT = RLM_TMAX / RLM_MT;  // keys per thread and slice
   const GMem<K> *src = (const GMem<K> *)src_;
   GMem<K> *dst = (GMem<K> *)dst_;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const uint32_t T = lv.T;
   K *bufA = (K *)smem_raw;
   K *bufB = bufA + T;
-  uint32_t *seg = (uint32_t *)(bufB + T);  // T + 1 entries
+  // segment starts relative to the slice (< T, so 16 bits): first the
+  // pieces' offsets, then the merge's segments
+  uint16_t *seg = (uint16_t *)(bufB + T);  // T + 1 entries
   __shared__ uint32_t tmp[RLM_MT / 64];
-  __shared__ uint32_t shv[4];
+  __shared__ uint32_t shd[2];
   const uint32_t tid = threadIdx.x;
-  const uint32_t nc = w.hdr->nChildren, ns = w.hdr->cnt[3];
+  const uint32_t ns = w.hdr->cnt[3];
   for (uint32_t item = blockIdx.x; item < ns; item += gridDim.x) {
-    uint32_t lo_c = 0, hi_c = nc;
-    while (hi_c - lo_c > 1) {
-      const uint32_t mid = (lo_c + hi_c) >> 1;
-      if (w.children[mid].sliceBase <= item) lo_c = mid; else hi_c = mid;
-    }
-    const RGroup C = w.children[lo_c];
+    const RGroup C = w.children[w.sliceOwner[item]];
     const RGroup P = w.groups[C.parent];
     const uint32_t S = (P.size + T - 1) / T;
     const uint32_t *Q = w.q + C.qBase;
@@ -478,44 +772,66 @@ __global__ void __launch_bounds__(RLM_MT) k_rlm_merge(RWs w, RLev lv, const void
     if (Q[S] != C.size) continue;  // the piece offsets raised an error already
     const uint32_t a = (item - C.sliceBase) * T;
     const uint32_t len = C.size - a < T ? C.size - a : T;
-    // pieces overlapping [a, a + len): i0 = last i with Q[i] <= a,
-    // i1 = first i with Q[i] >= a + len
-    if (tid == 0) {
-      uint32_t l = 0, h = S + 1;
-      while (h - l > 1) {
-        const uint32_t m = (l + h) >> 1;
-        if (Q[m] <= a) l = m; else h = m;
-      }
-      uint32_t l2 = l, h2 = S;
-      while (l2 < h2) {
-        const uint32_t m = (l2 + h2) >> 1;
-        if (Q[m] >= a + len) h2 = m; else l2 = m + 1;
-      }
-      shv[0] = l;
-      shv[1] = l2 > l ? l2 : l + 1;
+    // pieces overlapping [a, a + len), found by k_rlm_pieces
+    const uint32_t i0 = w.sliceI0[item], i1 = w.sliceI1[item];
+    if (i0 >= i1 || i1 > S) {  // cannot happen
+      if (tid == 0) rlm_error(w, AMS_DEVERR_RANGE);
+      continue;
     }
-    __syncthreads();
-    const uint32_t i0 = shv[0], i1 = shv[1];
     const uint32_t np = i1 - i0;
+    // piece offsets relative to the slice: max(Q[i] - a, 0), at most len;
+    // the first piece starts a - Q[i0] keys before the slice
     const bool cached = np <= T;
     if (cached)
-      for (uint32_t k = tid; k <= np; k += RLM_MT) seg[k] = Q[i0 + k];
-    __syncthreads();
-    // gather: element x of the slice comes from the piece holding a + x
-    uint32_t *flag = (uint32_t *)bufB;
-    for (uint32_t x = tid; x < len; x += RLM_MT) {
-      const uint32_t g = a + x;
-      const uint32_t k = cached ? upper_le<K>(seg, np, g) : upper_le<K>(Q + i0, np, g);
-      const uint32_t i = i0 + k;
-      const uint32_t qi = cached ? seg[k] : Q[i];
-      const uint32_t pos = cut[i] + (g - qi);
-      if (pos < seq_len(P, i, T)) {
-        bufA[x] = Key<KT>::enc(src[P.start + (size_t)i * T + pos]);
-      } else {  // cannot happen when the cuts and offsets agree
-        bufA[x] = 0;
-        rlm_error(w, AMS_DEVERR_RANGE);
+      for (uint32_t k = tid; k <= np; k += RLM_MT) {
+        const uint32_t q = Q[i0 + k];
+        seg[k] = (uint16_t)(q > a ? (q - a < len ? q - a : len) : 0u);
       }
-      flag[x] = (x == 0 || qi == g) ? 1u : 0u;
+    if (tid == 0) shd[0] = a - Q[i0];
+    __syncthreads();
+    const uint32_t lead = shd[0];
+    // gather: key x of the slice comes from the piece holding a + x; the
+    // piece searches first, then all loads in flight together
+    uint32_t *flag = (uint32_t *)bufB;
+    uint32_t pi[PT], pp[PT];
+    bool ok[PT];
+#pragma unroll
+    for (uint32_t u = 0; u < PT; ++u) {
+      const uint32_t x = tid + u * RLM_MT;
+      ok[u] = x < len;
+      uint32_t k = 0, rel = 0;
+      if (ok[u]) {
+        if (cached) {
+          uint32_t l = 0, h = np;  // last k with seg[k] <= x
+          while (h - l > 1) {
+            const uint32_t m = (l + h) >> 1;
+            if (seg[m] <= x) l = m; else h = m;
+          }
+          k = l;
+          rel = seg[k];
+        } else {
+          k = upper_le<K>(Q + i0, np, a + x);
+          rel = Q[i0 + k] > a ? Q[i0 + k] - a : 0u;
+        }
+      }
+      const uint32_t i = i0 + k;
+      // position in sequence i: the piece's cut plus the keys of the piece
+      // before x (the first piece also counts those before the slice)
+      const uint32_t pos = cut[i] + (x - rel) + (k == 0 ? lead : 0u);
+      pi[u] = i;
+      pp[u] = pos;
+      ok[u] = ok[u] && pos < seq_len(P, i, T);
+      if (x < len && !ok[u]) rlm_error(w, AMS_DEVERR_RANGE);  // cannot happen
+      if (x < len) flag[x] = (x == 0 || (k != 0 && rel == x)) ? 1u : 0u;  // a piece starts here
+    }
+    K v[PT];
+#pragma unroll
+    for (uint32_t u = 0; u < PT; ++u)
+      v[u] = ok[u] ? Key<KT>::enc(src[P.start + (size_t)pi[u] * T + pp[u]]) : (K)0;
+#pragma unroll
+    for (uint32_t u = 0; u < PT; ++u) {
+      const uint32_t x = tid + u * RLM_MT;
+      if (x < len) bufA[x] = v[u];
     }
     __syncthreads();
     const uint32_t nseg = block_exscan<RLM_MT>(flag, len, tmp);
@@ -523,9 +839,9 @@ __global__ void __launch_bounds__(RLM_MT) k_rlm_merge(RWs w, RLev lv, const void
     for (uint32_t x = tid; x < len; x += RLM_MT) {
       const uint32_t rk = flag[x];
       const uint32_t nx = x + 1 < len ? flag[x + 1] : nseg;
-      if (nx != rk) seg[rk] = x;
+      if (nx != rk) seg[rk] = (uint16_t)x;
     }
-    if (tid == 0) seg[nseg] = len;
+    if (tid == 0) seg[nseg] = (uint16_t)len;
     __syncthreads();
     // pairwise merge rounds: segments (2m, 2m+1) -> m, A first on ties
     uint32_t nsg = nseg;
@@ -544,7 +860,7 @@ __global__ void __launch_bounds__(RLM_MT) k_rlm_merge(RWs w, RLev lv, const void
         }
         const uint32_t m = l;
         const uint32_t as = seg[2 * m];
-        const uint32_t ae = 2 * m + 1 <= nsg ? seg[2 * m + 1] : len;
+        const uint32_t ae = seg[2 * m + 1];
         const uint32_t be = 2 * m + 2 <= nsg ? seg[2 * m + 2] : ae;
         const uint32_t na = ae - as, nb = be - ae;
         const K *A = in + as, *B = in + ae;
@@ -566,13 +882,13 @@ __global__ void __launch_bounds__(RLM_MT) k_rlm_merge(RWs w, RLev lv, const void
       __syncthreads();
       // segments of the next round: every other boundary
       const uint32_t nn = (nsg + 1) / 2;
-      uint32_t v[8];
+      uint32_t sv[8];
       uint32_t cntv = 0;
-      for (uint32_t k = tid; k < nn && cntv < 8; k += RLM_MT) v[cntv++] = seg[2 * k];
+      for (uint32_t k = tid; k < nn && cntv < 8; k += RLM_MT) sv[cntv++] = seg[2 * k];
       __syncthreads();
       cntv = 0;
-      for (uint32_t k = tid; k < nn && cntv < 8; k += RLM_MT) seg[k] = v[cntv++];
-      if (tid == 0) seg[nn] = len;
+      for (uint32_t k = tid; k < nn && cntv < 8; k += RLM_MT) seg[k] = (uint16_t)sv[cntv++];
+      if (tid == 0) seg[nn] = (uint16_t)len;
       __syncthreads();
       nsg = nn;
       K *t = in;
@@ -616,9 +932,14 @@ struct RPlan {
   uint32_t maxGroups, maxChildren, maxCut, maxBlk, maxQ, maxSlice;
   uint32_t itmax[RLM_MAXLEV];
   bool multiblock[RLM_MAXLEV];
-  size_t o_hdr, o_tmp, o_tile, o_g0, o_g1, o_sel, o_lo, o_hi, o_cc, o_cut, o_bl, o_br, o_q,
-      o_scr, bytes;
+  size_t o_hdr, o_tmp, o_tile, o_g0, o_g1, o_sel, o_lo, o_hi, o_cc, o_cut, o_bl, o_bown, o_sown,
+      o_si0, o_si1, o_q, o_scr, bytes;
 };
+
+// Steps a selection over N keys may take: with RLM_M pivots per step the
+// windows shrink about (RLM_M + 1)-fold per step, so about log2(N) / 3
+// steps are expected; this bound leaves ample room.
+uint32_t sel_steps(uint64_t N) { return (64 - __builtin_clzll(N | 1)) / 2 + 12; }
 
 uint32_t host_parts(uint64_t N, uint32_t r, uint32_t T) {
   if (N > (uint64_t)r * T) return r;
@@ -680,8 +1001,8 @@ ams_status make_rlm_plan(RPlan &pl, ams_key_t t, uint64_t n, const ams_rlm_param
     }
     uint64_t maxS = 0;
     for (uint64_t N : sizes) maxS = std::max(maxS, (N + pl.T - 1) / pl.T);
-    pl.multiblock[L] = maxS > RLM_NT;
-    pl.itmax[L] = 3 * (64 - __builtin_clzll(mx)) + 16;
+    pl.multiblock[L] = maxS > RLM_WAVE_SEQ;
+    pl.itmax[L] = sel_steps(mx);
     pl.maxChildren = std::max<uint32_t>(pl.maxChildren, (uint32_t)next.size());
     pl.maxCut = std::max<uint32_t>(pl.maxCut, (uint32_t)cut);
     pl.maxBlk = std::max<uint32_t>(pl.maxBlk, (uint32_t)blk);
@@ -707,10 +1028,13 @@ ams_status make_rlm_plan(RPlan &pl, ams_key_t t, uint64_t n, const ams_rlm_param
   pl.o_sel = take((size_t)pl.maxChildren * sizeof(RSel));
   pl.o_lo = take((size_t)pl.maxCut * 4);
   pl.o_hi = take((size_t)pl.maxCut * 4);
-  pl.o_cc = take((size_t)pl.maxCut * 4);
+  pl.o_cc = take((size_t)RLM_M * pl.maxCut * 4);
   pl.o_cut = take((size_t)pl.maxCut * 4);
-  pl.o_bl = take((size_t)pl.maxBlk * 4);
-  pl.o_br = take((size_t)pl.maxBlk * 4);
+  pl.o_bl = take((size_t)(RLM_M + 1) * pl.maxBlk * 4);
+  pl.o_bown = take((size_t)pl.maxBlk * 4);
+  pl.o_sown = take((size_t)pl.maxSlice * 4);
+  pl.o_si0 = take((size_t)pl.maxSlice * 4);
+  pl.o_si1 = take((size_t)pl.maxSlice * 4);
   pl.o_q = take((size_t)pl.maxQ * 4);
   pl.o_scr = take((ng + 1) * 4);
   pl.bytes = o;
@@ -719,6 +1043,23 @@ ams_status make_rlm_plan(RPlan &pl, ams_key_t t, uint64_t n, const ams_rlm_param
 
 uint32_t grid_cap(uint64_t items, uint32_t cap) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(items, cap));
+}
+
+// All selections of a level: the wave kernel runs the small groups' whole
+// selections in one launch, the block kernel one step of the large groups'
+// per launch.
+template <int KT>
+void select_level(const RWs &w, const RLev &lv, const void *src, uint32_t maxChildren,
+                  uint32_t maxBlk, bool multiblock, hipStream_t s) {
+  hipLaunchKernelGGL(k_rlm_sel_init<KT>, dim3(grid_cap(maxChildren, 2048)), dim3(RLM_NT), 0, s, w,
+                     lv, src);
+  hipLaunchKernelGGL(k_rlm_select_wave<KT>, dim3(grid_cap((maxChildren + 3) / 4, 4096)),
+                     dim3(RLM_NT), 0, s, w, lv, src);
+  if (multiblock)
+    for (uint32_t it = 0; it < lv.itmax; ++it)
+      hipLaunchKernelGGL(k_rlm_select_blocks<KT>, dim3(grid_cap(maxBlk, 4096)), dim3(RLM_NT), 0, s,
+                         w, lv, src);
+  hipLaunchKernelGGL(k_rlm_cut, dim3(grid_cap(maxChildren, 2048)), dim3(RLM_NT), 0, s, w, lv);
 }
 
 template <int KT>
@@ -735,8 +1076,12 @@ ams_status rlm_typed(const RPlan &pl, const void *in, void *out, void *wsv, hipS
   w.cc = (uint32_t *)(base + pl.o_cc);
   w.cut = (uint32_t *)(base + pl.o_cut);
   w.bl = (uint32_t *)(base + pl.o_bl);
-  w.br = (uint32_t *)(base + pl.o_br);
+  w.blkOwner = (uint32_t *)(base + pl.o_bown);
+  w.sliceOwner = (uint32_t *)(base + pl.o_sown);
+  w.sliceI0 = (uint32_t *)(base + pl.o_si0);
+  w.sliceI1 = (uint32_t *)(base + pl.o_si1);
   w.q = (uint32_t *)(base + pl.o_q);
+  w.capCut = pl.maxCut;
   w.scratch = (uint32_t *)(base + pl.o_scr);
   void *tmp = base + pl.o_tmp;
   // buffer of level l's output: the last level writes `out`
@@ -745,7 +1090,7 @@ ams_status rlm_typed(const RPlan &pl, const void *in, void *out, void *wsv, hipS
   ams_status st = run_tile_sort(KT, false, in, nullptr, buf(0), nullptr, pl.n, pl.T,
                                 base + pl.o_tile, s);
   if (st) return st;
-  const size_t ldsM = 2 * (size_t)pl.T * sizeof(K) + ((size_t)pl.T + 1) * 4;
+  const size_t ldsM = 2 * (size_t)pl.T * sizeof(K) + ((size_t)pl.T + 1) * 2;
   (void)hipFuncSetAttribute((const void *)k_rlm_merge<KT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsM);
   for (uint32_t l = 0; l < pl.L; ++l) {
@@ -767,17 +1112,12 @@ ams_status rlm_typed(const RPlan &pl, const void *in, void *out, void *wsv, hipS
     {
       TraceScope ts("rlm_children", l, s);
       hipLaunchKernelGGL(k_rlm_children, dim3(1), dim3(1024), 0, s, w, lv);
+      hipLaunchKernelGGL(k_rlm_owners, dim3(grid_cap(pl.maxChildren, 2048)), dim3(RLM_NT), 0, s, w,
+                         lv);
     }
     {
       TraceScope ts("rlm_select", l, s);
-      hipLaunchKernelGGL(k_rlm_sel_init<KT>, dim3(grid_cap(pl.maxChildren, 2048)), dim3(RLM_NT), 0,
-                         s, w, lv, src);
-      const uint32_t steps = pl.multiblock[l] ? pl.itmax[l] : 1u;
-      for (uint32_t it = 0; it < steps; ++it)
-        hipLaunchKernelGGL(k_rlm_select<KT>, dim3(grid_cap(pl.maxBlk, 4096)), dim3(RLM_NT), 0, s,
-                           w, lv, src);
-      hipLaunchKernelGGL(k_rlm_cut, dim3(grid_cap(pl.maxChildren, 2048)), dim3(RLM_NT), 0, s, w,
-                         lv);
+      select_level<KT>(w, lv, src, pl.maxChildren, pl.maxBlk, pl.multiblock[l], s);
     }
     {
       TraceScope ts("rlm_pieces", l, s);
@@ -834,9 +1174,10 @@ ams_status step_select_typed(const void *d_runs, uint64_t n, uint32_t T, uint32_
   pl.o_sel = take(parts * sizeof(RSel));
   pl.o_lo = take(cut * 4);
   pl.o_hi = take(cut * 4);
-  pl.o_cc = take(cut * 4);
-  pl.o_bl = take(blk * 4);
-  pl.o_br = take(blk * 4);
+  pl.o_cc = take(RLM_M * cut * 4);
+  pl.o_bl = take((RLM_M + 1) * blk * 4);
+  pl.o_bown = take(blk * 4);
+  pl.o_sown = take((S + parts) * 4);
   pl.o_scr = take((parts + 2) * 4);
   void *ws = nullptr;
   if (hipMallocAsync(&ws, o, s) != hipSuccess) {
@@ -855,14 +1196,16 @@ ams_status step_select_typed(const void *d_runs, uint64_t n, uint32_t T, uint32_
   w.cc = (uint32_t *)(base + pl.o_cc);
   w.cut = d_cuts;  // rows j = 0..parts-1 land in the caller's table directly
   w.bl = (uint32_t *)(base + pl.o_bl);
-  w.br = (uint32_t *)(base + pl.o_br);
+  w.blkOwner = (uint32_t *)(base + pl.o_bown);
+  w.sliceOwner = (uint32_t *)(base + pl.o_sown);
+  w.capCut = (uint32_t)cut;
   w.scratch = (uint32_t *)(base + pl.o_scr);
   RLev lv;
   memset(&lv, 0, sizeof lv);
   lv.T = T;
   lv.r = parts;
   lv.force = parts;
-  lv.itmax = 3 * (64 - __builtin_clzll(n)) + 16;
+  lv.itmax = sel_steps(n);
   lv.capChildren = parts;
   lv.capCut = (uint32_t)cut;
   lv.capBlk = (uint32_t)blk;
@@ -871,13 +1214,8 @@ ams_status step_select_typed(const void *d_runs, uint64_t n, uint32_t T, uint32_
   lv.seed = seed ? seed : 14106754ull;
   hipLaunchKernelGGL(k_rlm_root, dim3(1), dim3(64), 0, s, w, (uint32_t)n);
   hipLaunchKernelGGL(k_rlm_children, dim3(1), dim3(1024), 0, s, w, lv);
-  hipLaunchKernelGGL(k_rlm_sel_init<KT>, dim3(grid_cap(parts, 2048)), dim3(RLM_NT), 0, s, w, lv,
-                     d_runs);
-  const uint32_t steps = S > RLM_NT ? lv.itmax : 1u;
-  for (uint32_t it = 0; it < steps; ++it)
-    hipLaunchKernelGGL(k_rlm_select<KT>, dim3(grid_cap(blk, 4096)), dim3(RLM_NT), 0, s, w, lv,
-                       d_runs);
-  hipLaunchKernelGGL(k_rlm_cut, dim3(grid_cap(parts, 2048)), dim3(RLM_NT), 0, s, w, lv);
+  hipLaunchKernelGGL(k_rlm_owners, dim3(grid_cap(parts, 2048)), dim3(RLM_NT), 0, s, w, lv);
+  select_level<KT>(w, lv, d_runs, parts, (uint32_t)blk, S > RLM_WAVE_SEQ, s);
   hipLaunchKernelGGL(k_rlm_last_row, dim3(grid_cap((S + 255) / 256, 1024)), dim3(256), 0, s,
                      d_cuts, parts, (uint32_t)S, n, T);
   uint32_t bits = 0;

@@ -123,3 +123,24 @@ def test_bench_plan_config1(api):
     assert st["levels"] == 1 and st["subproblems"][0] == 1 and st["subproblems"][1] == 0
     assert st["leaf_keys"] + st["big_keys"] == n
     assert_same_bits(got, want, name)
+
+
+def test_rlm_2p28_matches_oracle(api, u64_2p28):
+    """RLM-sort (Section 5) of the default workload's keys: the same unique
+    sorted output."""
+    keys, want = u64_2p28
+    n, kt, dist, pkw, cfg = bench.RLM_WORKLOADS["rlm_uniform_u64_2^28"]
+    p = api.rlm_params(**pkw)
+    ws = api.alloc_workspace(api.rlm_workspace_bytes(kt, n, p))
+    log("rlm_uniform_u64_2^28 on the GPU")
+    d = to_dev(keys)
+    got = host(api.rlm_sort_keys(d, params=p, workspace=ws))
+    assert_same_bits(got, want, "rlm 2^28")
+
+
+def test_rlm_2p20_matches_oracle(api):
+    n, kt, dist, pkw, cfg = bench.RLM_WORKLOADS["rlm_uniform_u64_2^20"]
+    keys = W.keys(kt, n, W.rng_for(cfg), dist)
+    want, _ = oracle.oracle_sort(kt, keys)
+    got = host(api.rlm_sort_keys(to_dev(keys), params=api.rlm_params(**pkw)))
+    assert_same_bits(got, want, "rlm 2^20")
