@@ -108,6 +108,12 @@ typedef struct {
 #define AMS_FLAG_SAMPLED_LEAF_SPLIT 4u /* base case: split every leaf by sampled splitters
                                           instead of first trying its key range; the sorted
                                           output is the same either way (test hook) */
+#define AMS_FLAG_STRATIFIED 32u /* below the first level, each subproblem's splitters follow
+                                   the buckets its group brought from the level above
+                                   (Section 6: the overpartitioning exploited in the
+                                   recursion): every bucket boundary is kept as a splitter
+                                   and the buckets are shared among them in proportion to
+                                   their exact sizes; the sorted output is the same */
 #define AMS_FLAG_CHECK 8u /* the call waits for its stream before returning and returns
                              AMS_EDEVICE if its kernels raised a device error */
 #define AMS_FLAG_TEST_TINY_TABLES 16u /* test hook: the leaf list holds one entry, so any

@@ -33,6 +33,7 @@ AMS_FLAG_STABLE_PARTITION = 2
 AMS_FLAG_SAMPLED_LEAF_SPLIT = 4
 AMS_FLAG_CHECK = 8
 AMS_FLAG_TEST_TINY_TABLES = 16
+AMS_FLAG_STRATIFIED = 32
 
 AMS_DEVERR_TABLE = 1
 AMS_DEVERR_ACTIVE = 2

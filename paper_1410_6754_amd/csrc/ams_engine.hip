@@ -67,6 +67,19 @@ AMS_DEV void raise_error(Ctr *c, uint32_t bits) {
   atomicOr(&g_dev_errors, bits);
 }
 
+// The buckets a group of one level brings to the next level (the paper's
+// overpartitioning, Section 6: a group holds about b consecutive buckets of
+// known size).  Up to STRATA_MAX strata of consecutive buckets, each with
+// its exact key count; stratum j holds the keys x with thr[j-1] < x <=
+// thr[j] (ord values; the last stratum is unbounded above).
+constexpr uint32_t STRATA_MAX = 16;
+struct Strata {
+  uint64_t thr[STRATA_MAX];
+  uint32_t cnt[STRATA_MAX];
+  uint32_t k;  // strata (0: none recorded)
+  uint32_t pad;
+};
+
 struct Ws {
   Root *roots;
   uint32_t nroots;
@@ -85,6 +98,7 @@ struct Ws {
   uint32_t *cstart;
   uint8_t *cdst;
   uint32_t *nch;
+  Strata *strata;  // per active subproblem of the next level: its parent buckets
   uint32_t capTile, capBlk, capSBlk;
   uint32_t *dbgHist, *dbgChildren, *dbgNChild;
 };
@@ -93,6 +107,9 @@ struct Lev {
   uint32_t level, L, last, shrink;
   uint32_t rmax, b, a, mmax, Smax, TC, TB, HS, CH, rankG;
   uint32_t C, flags, Scap;
+  uint32_t strata;      // this level's splitters follow the strata its subproblems carry
+  uint32_t strataNext;  // the grouping records strata for the next level
+  uint32_t kw;          // key bytes
   uint32_t capTile, capBlk, capSBlk;  // the level's table capacities
   uint64_t seed;
 };
@@ -201,24 +218,31 @@ AMS_DEV void push_leaf(const Ws &w, Seg s, PlaceStats &ps) {
 // A root or child of N keys entering level lv: a leaf when it fits the base
 // case, an oversized leaf when no partition level is left, otherwise an
 // active subproblem of level lv.
-AMS_DEV void place_subproblem(const Ws &w, const LevTable &lt, uint32_t L, uint32_t lv,
-                              uint32_t off, uint32_t N, uint32_t root, uint32_t buf, bool inplace,
-                              uint32_t C, PlaceStats &ps) {
-  if (N == 0) return;
+// Returns the subproblem's slot in the level's active list, or 0xFFFFFFFF
+// when it became a leaf.
+AMS_DEV uint32_t place_subproblem(const Ws &w, const LevTable &lt, uint32_t L, uint32_t lv,
+                                  uint32_t off, uint32_t N, uint32_t root, uint32_t buf,
+                                  bool inplace, uint32_t C, PlaceStats &ps) {
+  if (N == 0) return 0xFFFFFFFFu;
   if (N <= C) {
     push_leaf(w, Seg{off, N, root, make_meta(buf, LEAF_REG, 0, 0, 0)}, ps);
-    return;
+    return 0xFFFFFFFFu;
   }
   if (lv >= L) {
     push_leaf(w, Seg{off, N, root, make_meta(buf, LEAF_BIG, 0, 0, 0)}, ps);
-    return;
+    return 0xFFFFFFFFu;
   }
   const Lev &l = lt.l[lv];
   uint32_t logr, logm, S;
   seg_shape(N, C, l.shrink != 0, l.rmax, l.b, l.a, l.Scap, logr, logm, S);
   uint32_t slot = atomicAdd(&w.ctr->nact[lv], 1u);
   Seg s{off, N, root, make_meta(buf, 0, dst_for(buf, inplace, L, lv), logm, logr)};
-  if (slot < w.capAct[lv]) w.act[lv][slot] = s; else raise_error(w.ctr, 1u);
+  if (slot < w.capAct[lv]) {
+    w.act[lv][slot] = s;
+    return slot;
+  }
+  raise_error(w.ctr, 1u);
+  return 0xFFFFFFFFu;
 }
 
 // ---------------------------------------------------------------------------
@@ -377,6 +401,106 @@ template <int KT> __global__ void __launch_bounds__(256) k_sample_rank(Ws w, Lev
           tree[eytzinger_slot(sp, m)] = x;
         }
       }
+    }
+    __syncthreads();
+  }
+}
+
+// Splitters of a subproblem that carries strata from the level above
+// (exploiting the overpartitioning in the recursion, Section 6): the sample
+// is sorted whole, the m buckets are shared among the strata in proportion
+// to their exact key counts, every stratum boundary becomes a splitter, and
+// each stratum's own buckets take equidistant ranks of the sample keys that
+// fall into it.  Without strata this is the plain rule (rank j*a - 1).  One
+// workgroup per subproblem.
+template <int KT> __global__ void __launch_bounds__(256) k_sample_strata(Ws w, Lev lv) {
+  typedef typename Key<KT>::T K;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ uint32_t sR[STRATA_MAX + 1], sM[STRATA_MAX + 1];
+  __shared__ K sT[STRATA_MAX];
+  __shared__ uint32_t sk;
+  K *sh = (K *)smem_raw;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t P = w.ctr->P;
+  for (uint32_t i = blockIdx.x; i < P; i += gridDim.x) {
+    const uint32_t nb = w.sampStart[i + 1] - w.sampStart[i];
+    const Seg s = w.act[lv.level][i];
+    const uint32_t S = nb * 256;
+    const uint32_t m = 1u << meta_logm(s.meta);
+    K *srt = sh + lv.Smax;
+    const K *src = (const K *)w.samp + (size_t)i * lv.Smax;
+    for (uint32_t q = tid; q < S; q += 256) sh[q] = src[q];
+    __syncthreads();
+    // the whole sample sorted: rank across the sorted blocks (equal keys by
+    // block, then by position), each element written at its rank
+    for (uint32_t q = tid; q < S; q += 256) {
+      const uint32_t j = q >> 8;
+      const K x = sh[q];
+      uint32_t rank = q & 255u;
+      for (uint32_t jb = 0; jb < nb; ++jb) {
+        if (jb == j) continue;
+        const K *blk = sh + jb * 256;
+        rank += (jb < j) ? count_less_eq(blk, 256u, x) : count_less(blk, 256u, x);
+      }
+      srt[rank] = x;
+    }
+    // strata: thresholds, sample keys below each, buckets per stratum
+    if (tid == 0) {
+      const Strata *st = w.strata + i;
+      uint32_t k = lv.strata ? st->k : 0u;
+      if (k == 0) k = 1;
+      uint64_t cum = 0;
+      const uint64_t N = s.size;
+      sM[0] = 0;
+      for (uint32_t b = 0; b < k; ++b) {
+        const uint32_t c = k == 1 ? s.size : st->cnt[b];
+        cum += c;
+        sM[b + 1] = b + 1 == k ? m : (uint32_t)((cum * m) / N);
+        if (b + 1 < k) sT[b] = (K)st->thr[b];
+      }
+      // every stratum keeps at least one bucket (its upper boundary)
+      for (uint32_t b = 1; b <= k; ++b)
+        if (sM[b] <= sM[b - 1]) sM[b] = sM[b - 1] + 1;
+      if (sM[k] > m) k = 1, sM[1] = m;  // cannot happen with the strata's sizes
+      sk = k;
+    }
+    __syncthreads();
+    const uint32_t k = sk;
+    // sample keys in strata below b: those <= thr[b-1]
+    for (uint32_t b = tid; b <= k; b += 256) {
+      if (b == 0) sR[0] = 0;
+      else if (b == k) sR[k] = S;
+      else {
+        uint32_t lo = 0, hi = S;  // first rank with srt > thr
+        const K t = sT[b - 1];
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (srt[mid] <= t) lo = mid + 1; else hi = mid;
+        }
+        sR[b] = lo;
+      }
+    }
+    __syncthreads();
+    K *spl = (K *)w.spl + (size_t)i * lv.mmax;
+    K *tree = (K *)w.tree + (size_t)i * lv.mmax;
+    for (uint32_t sp = 1 + tid; sp < m; sp += 256) {
+      uint32_t b = 0;  // stratum owning slot sp: sM[b] < sp <= sM[b+1]
+      while (b + 1 < k && sM[b + 1] < sp) ++b;
+      K x;
+      if (sp == sM[b + 1] && b + 1 < k) {
+        x = sT[b];  // the stratum's upper boundary
+      } else {
+        const uint32_t mb = sM[b + 1] - sM[b], sb = sR[b + 1] - sR[b];
+        const uint32_t ii = sp - sM[b];  // 1 .. mb-1
+        if (sb) {
+          const uint32_t r = (uint32_t)(((uint64_t)ii * sb + mb - 1) / mb);  // ceil(ii sb / mb)
+          x = srt[sR[b] + (r ? r - 1 : 0)];
+        } else {
+          x = b + 1 < k ? sT[b] : (b ? sT[b - 1] : srt[S - 1]);
+        }
+      }
+      spl[sp - 1] = x;
+      tree[eytzinger_slot(sp, m)] = x;
     }
     __syncthreads();
   }
@@ -797,6 +921,62 @@ AMS_DEV uint32_t build_children(const PackSmem &p, uint32_t NB, uint32_t L, uint
   return np <= CH ? nch : CH + 1;  // CH + 1: cannot happen, reported as an overflow
 }
 
+// Strata of one group for the next level: its consecutive bucket ids
+// [f, e) cut greedily into at most STRATA_MAX runs of about size /
+// STRATA_MAX keys each (a short last run joins the one before).  The cut
+// before id j is a key threshold: without equality buckets id j holds
+// s_j < x <= s_{j+1}, so ids below j hold x <= s_j; with them, ids below
+// 2b+1 hold x < s_{b+1} and ids below 2b+2 hold x <= s_{b+1}.
+template <typename K>
+AMS_DEV void record_strata_t(const Ws &w, const Lev &lv, uint32_t i, uint32_t m, bool eq,
+                             const uint32_t *tot, uint32_t f, uint32_t e, uint32_t size,
+                             uint32_t slot) {
+  const K *spl = (const K *)w.spl + (size_t)i * lv.mmax;
+  Strata *st = w.strata + slot;
+  const uint32_t target = (size + STRATA_MAX - 1) / STRATA_MAX;
+  uint32_t k = 0, acc = 0;
+  for (uint32_t id = f; id < e; ++id) {
+    acc += tot[id];
+    if (acc >= target && k + 1 < STRATA_MAX && id + 1 < e) {
+      // threshold before id + 1
+      const uint32_t j = id + 1;
+      bool ok = true;
+      uint64_t thr;
+      if (!eq) {
+        thr = (uint64_t)spl[j - 1];
+      } else if (j & 1u) {  // j = 2b+1: ids below hold x < s_{b+1}
+        const K v = spl[j >> 1];
+        ok = v != 0;
+        thr = (uint64_t)v - 1;
+      } else {  // j = 2b+2: ids below hold x <= s_{b+1}
+        thr = (uint64_t)spl[(j >> 1) - 1];
+      }
+      if (ok) {
+        st->thr[k] = thr;
+        st->cnt[k] = acc;
+        ++k;
+        acc = 0;
+      }
+    }
+  }
+  st->cnt[k] = acc;
+  ++k;
+  // a last stratum of less than half the target joins the one before
+  if (k >= 2 && st->cnt[k - 1] < target / 2) {
+    st->cnt[k - 2] += st->cnt[k - 1];
+    --k;
+  }
+  st->k = k;
+  (void)m;
+}
+
+AMS_DEV void record_strata(const Ws &w, const Lev &lv, uint32_t i, uint32_t m, bool eq,
+                           const uint32_t *tot, uint32_t f, uint32_t e, uint32_t size,
+                           uint32_t slot) {
+  if (lv.kw == 8) record_strata_t<uint64_t>(w, lv, i, m, eq, tot, f, e, size, slot);
+  else record_strata_t<uint32_t>(w, lv, i, m, eq, tot, f, e, size, slot);
+}
+
 __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const uint32_t HS = lv.HS, CH = lv.CH;
@@ -888,7 +1068,10 @@ __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
       if (p.kind[c] == CHILD_REG) {
         cd = dst;
         maxChild = size > maxChild ? size : maxChild;
-        place_subproblem(w, lt, lv.L, lv.level + 1, off, size, s.root, cd, inplace, lv.C, ps);
+        const uint32_t slot =
+            place_subproblem(w, lt, lv.L, lv.level + 1, off, size, s.root, cd, inplace, lv.C, ps);
+        if (lv.strataNext && slot != 0xFFFFFFFFu)
+          record_strata(w, lv, i, m, eq, p.tot, p.first[c], p.end[c], size, slot);
       } else {
         cd = finToOut ? BUF_OUT : dst;
         if (cd != BUF_OUT) {
@@ -2864,6 +3047,12 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
   pl.o_cstart = take(eCS * 4);
   pl.o_cdst = take(eCD);
   pl.o_nch = take(any ? (size_t)capAct * 4 : 0);
+  {
+    size_t ns = 0;  // strata of the subproblems of every level below the first
+    if (pl.flags & AMS_FLAG_STRATIFIED)
+      for (uint32_t l = 1; l < L; ++l) ns = std::max(ns, (size_t)pl.lev[l].P);
+    pl.o_strata = take(ns * sizeof(Strata));
+  }
   pl.o_dbg = take((size_t)(nroots + 1) * 8);  // batch offsets upload / step outputs
   pl.bytes = o;
   return AMS_OK;
@@ -2899,6 +3088,7 @@ static Ws carve(const Plan &pl, char *base) {
   w.cstart = (uint32_t *)(base + pl.o_cstart);
   w.cdst = (uint8_t *)(base + pl.o_cdst);
   w.nch = (uint32_t *)(base + pl.o_nch);
+  w.strata = (Strata *)(base + pl.o_strata);
   w.capTile = pl.capTile;
   w.capBlk = pl.capBlk;
   w.capSBlk = pl.capSBlk;
@@ -2932,6 +3122,10 @@ static LevTable lev_table(const Plan &pl, bool shrink_last) {
     v.capBlk = ls.blocks;
     v.capSBlk = ls.sblocks;
     v.seed = pl.seed;
+    v.kw = pl.kw;
+    const bool strat = (pl.flags & AMS_FLAG_STRATIFIED) != 0;
+    v.strata = strat && l >= 1;
+    v.strataNext = strat && l + 1 < pl.L;
   }
   return lt;
 }
@@ -2983,12 +3177,20 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
         hipLaunchKernelGGL(k_sample_blocks<KT>, dim3(grid_for(ls.sblocks, 2048)), dim3(256), 0,
                            s, w, lv);
       }
-      size_t lds = (size_t)ls.Smax * sizeof(K);
-      allow_lds(k_sample_rank<KT>, lds);
-      uint32_t ng = (ls.Smax / 256 + ls.rankG - 1) / ls.rankG;
-      TraceScope ts("sample_rank", l, s);
-      hipLaunchKernelGGL(k_sample_rank<KT>, dim3(grid_for((uint64_t)ls.P * ng, 1024)), dim3(256),
-                         lds, s, w, lv);
+      if (lv.strata) {
+        size_t lds = 2 * (size_t)ls.Smax * sizeof(K);
+        allow_lds(k_sample_strata<KT>, lds);
+        TraceScope ts("sample_rank", l, s);
+        hipLaunchKernelGGL(k_sample_strata<KT>, dim3(grid_for(ls.P, 1024)), dim3(256), lds, s, w,
+                           lv);
+      } else {
+        size_t lds = (size_t)ls.Smax * sizeof(K);
+        allow_lds(k_sample_rank<KT>, lds);
+        uint32_t ng = (ls.Smax / 256 + ls.rankG - 1) / ls.rankG;
+        TraceScope ts("sample_rank", l, s);
+        hipLaunchKernelGGL(k_sample_rank<KT>, dim3(grid_for((uint64_t)ls.P * ng, 1024)),
+                           dim3(256), lds, s, w, lv);
+      }
     }
     size_t ldsC = 2 * (size_t)ls.mmax * sizeof(K) + (size_t)ls.HS * 4;
     allow_lds(k_count<KT>, ldsC);

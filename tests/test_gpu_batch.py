@@ -172,3 +172,19 @@ def test_autotune_rejects_bad_arguments(api):
         api.autotune(dk, [0, 10])
     with pytest.raises(AmsError):
         api.autotune(dk, [5, 1000])  # offsets must start at 0
+
+
+def test_batch_stratified_splitters(api):
+    """Batched segments with strata below the first level: each segment
+    equals the oracle."""
+    import oracle
+    rng = np.random.default_rng([W.BASE_SEED, 830])
+    sizes = W.batch_sizes(300, rng, 8, 20)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    keys = W.uniform_u64(int(offs[-1]), rng)
+    p = api.make_params(levels=2, flags=32)
+    out = to_host(api.sort_batch(to_dev(keys), offs, params=p))
+    for i in range(sizes.size):
+        a, b = int(offs[i]), int(offs[i + 1])
+        want, _ = oracle.oracle_sort(W.KEY_U64, keys[a:b])
+        assert np.array_equal(out[a:b], want), i

@@ -168,3 +168,43 @@ def test_sampled_leaf_split_full_sort(api, dist):
     p = api.make_params(levels=2, k=64, overpartition_b=4, flags=4)  # AMS_FLAG_SAMPLED_LEAF_SPLIT
     log("sampled leaf split %s n=%d" % (dist, n))
     check_sort_keys(api, U64, keys, params=p, what="sampled leaf split")
+
+
+# Splitters below the first level that follow the parent buckets (the
+# overpartitioning exploited in the recursion): same output on every shape.
+STRAT = 32  # AMS_FLAG_STRATIFIED
+
+
+@pytest.mark.parametrize("kt", [U64, U32, F32])
+@pytest.mark.parametrize("dist", ["uniform", "few", "zipf", "sorted", "reversed", "specials"])
+def test_stratified_splitters_keys(api, kt, dist):
+    n = 1_500_007
+    p = api.make_params(levels=2, k=64, overpartition_b=4, flags=STRAT)
+    log("stratified kt=%d %s n=%d" % (kt, dist, n))
+    check_sort_keys(api, kt, gen(kt, n, dist, 800), params=p, what="stratified " + dist)
+
+
+@pytest.mark.parametrize("levels,k,b", [(2, 256, 4), (3, 16, 4), (2, 128, 8)])
+def test_stratified_splitters_pairs(api, levels, k, b):
+    p = api.make_params(levels=levels, k=k, overpartition_b=b, flags=STRAT)
+    for dist in ("uniform", "few", "equal"):
+        log("stratified pairs levels=%d k=%d b=%d %s" % (levels, k, b, dist))
+        check_sort_pairs(api, U64, gen(U64, 2_000_003, dist, 810), params=p,
+                         what="stratified pairs " + dist)
+
+
+def test_stratified_splitters_large_with_stats(api):
+    """Two levels of k = 256, b = 4 on 2^24 + odd keys with strata below the
+    first level: the output is the oracle's, and every level-1 subproblem's
+    grouping still meets its lower bound L* >= ceil(W / r)."""
+    n = (1 << 24) + 4321
+    keys = gen(U64, n, "uniform", 820)
+    p = api.make_params(levels=2, k=256, overpartition_b=4, flags=STRAT)
+    ws = api.alloc_workspace(api.workspace_bytes(U64, n, False, p))
+    log("stratified 2^24+ with stats")
+    out = to_host(api.sort_keys(to_dev(keys), params=p, workspace=ws))
+    st = api.workspace_stats(ws)
+    import oracle
+    want, _ = oracle.oracle_sort(U64, keys)
+    assert np.array_equal(out, want)
+    assert st["levels"] == 2 and st["keys"][1] == n and st["imbalance_max"][1] >= 1.0
