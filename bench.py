@@ -288,6 +288,7 @@ def main() -> int:
               for l in range(st["levels"])]
     leaves = {"leaves": st["leaves"], "big_leaves": st["big_leaves"], "leaf_keys": st["leaf_keys"],
               "copy_keys": st["copy_keys"], "big_keys": st["big_keys"],
+              "merge_ranges": st["merge_ranges"], "merge_keys": st["merge_keys"],
               "device_errors": st["device_errors"]}
     if args.trace_file:
         with open(args.trace_file, "w") as f:
@@ -383,7 +384,8 @@ def pass_table(trace, st, w: int, kw: int, steps: int, ceiling_gbs: float):
     keys placed in final children at earlier levels have dropped out, and a
     level without subproblems launches its kernels on empty lists, which are
     left out.  Count reads each key once (w_key bytes), the scatter reads and
-    writes it (2w), the base case reads and writes the keys of its leaves.
+    writes it (2w), the base case reads and writes the keys of its leaves
+    (oversized leaves are first partitioned once more, a pass of their own).
     Returns (passes, per-kernel sums over the launches with work)."""
     by_name = {e["name"]: e for e in trace}
     passes = {}
@@ -420,6 +422,10 @@ def pass_table(trace, st, w: int, kw: int, steps: int, ceiling_gbs: float):
                 "implementation_bytes": (kw + 2 * w) * keys, "GB_per_s": round(gbs, 1),
                 "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
                 "implementation_GB_per_s": round((kw + 2 * w) * keys / (lm * 1e-3) / 1e9, 1)}
+    # oversized leaves: one more partition (a count read and a scatter, 2w
+    # algorithmic bytes per key like a level's pass); their pieces are then
+    # sorted by the base case with the other leaves
+    add("big_part", "big_part", st["big_keys"], 2 * w)
     add("finish", "finish", st["leaf_keys"] + st["copy_keys"] + st["big_keys"], 2 * w)
     return passes, alg
 

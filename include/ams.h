@@ -119,6 +119,9 @@ typedef struct {
 #define AMS_FLAG_TEST_TINY_TABLES 16u /* test hook: the leaf list holds one entry, so any
                                          sort with more than one leaf raises
                                          AMS_DEVERR_TABLE (its output is then invalid) */
+#define AMS_FLAG_TEST_NO_PIECE_ROOM 64u /* test hook: the pieces of oversized leaves find the
+                                           leaf list full and are finished by the remainder
+                                           pass (the sorted output is the same) */
 
 /* Bytes of device workspace a call with these arguments needs.  Returns 0 on
  * invalid arguments.  ams_sort_* accept d_ws = NULL, in which case they
@@ -252,10 +255,15 @@ typedef struct {
   double imbalance_max[4];    /* largest L* / ceil(W / r) over level l's subproblems */
   double imbalance_mean[4];   /* its mean over the subproblems with W > 0 */
   uint32_t leaves;            /* leaves the base-case kernel processed */
-  uint32_t big_leaves;        /* of those, larger than one workgroup's LDS (merged) */
+  uint32_t big_leaves;        /* of those, larger than one workgroup's LDS: each is
+                                 partitioned once more in HBM by its workgroup */
   uint64_t leaf_keys;         /* keys sorted in LDS by the base case */
   uint64_t copy_keys;         /* keys of final children copied to the output */
   uint64_t big_keys;          /* keys in oversized leaves */
+  uint32_t merge_ranges;      /* pieces of oversized leaves still larger than one
+                                 workgroup's LDS, sorted by the merge fallback */
+  uint32_t reserved;
+  uint64_t merge_keys;        /* keys in those pieces */
 } ams_run_stats;
 ams_status ams_workspace_stats(const void *d_ws, void *stream, ams_run_stats *out);
 

@@ -34,6 +34,7 @@ AMS_FLAG_SAMPLED_LEAF_SPLIT = 4
 AMS_FLAG_CHECK = 8
 AMS_FLAG_TEST_TINY_TABLES = 16
 AMS_FLAG_STRATIFIED = 32
+AMS_FLAG_TEST_NO_PIECE_ROOM = 64
 
 AMS_DEVERR_TABLE = 1
 AMS_DEVERR_ACTIVE = 2
@@ -112,6 +113,9 @@ class RunStats(ctypes.Structure):
         ("leaf_keys", ctypes.c_uint64),
         ("copy_keys", ctypes.c_uint64),
         ("big_keys", ctypes.c_uint64),
+        ("merge_ranges", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("merge_keys", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:

@@ -48,11 +48,14 @@ struct Ctr {
   uint32_t lv_maxchild[MAXLEV];  // largest regular child produced
   uint32_t lv_imb_max[MAXLEV];   // max of L* / ceil(W / r), 16.16 fixed point
   uint32_t lv_tiles[MAXLEV];     // tiles of the level pass
-  uint32_t pad[3];
+  uint32_t nmerge;               // ranges the merge fallback sorted
+  uint32_t nbl;                  // entries of the oversized-leaf list
+  uint32_t nrest;                // entries of the remainder list (k_big_rest)
   unsigned long long lv_keys[MAXLEV];     // keys in the partitioned subproblems
   unsigned long long lv_final[MAXLEV];    // keys placed in final children
   unsigned long long lv_imb_sum[MAXLEV];  // sum of the ratio over subproblems
   unsigned long long leaf_keys[3];        // keys in leaves, by leaf kind
+  unsigned long long merge_keys;          // keys the merge fallback sorted
 };
 static_assert(sizeof(Ctr) % 8 == 0 && offsetof(Ctr, lv_keys) % 8 == 0, "Ctr layout");
 
@@ -90,6 +93,8 @@ struct Ws {
   uint32_t capAct[MAXLEV + 1];
   Seg *leaves;
   uint32_t capLeaf;
+  Seg *bigLeaves;  // capBig oversized leaves (k_big_part), then 2 capBig remainder entries
+  uint32_t capBig;
   uint32_t *tileStart, *blkStart, *sampStart;
   void *samp, *spl, *tree;
   uint8_t *eqOn;
@@ -208,9 +213,14 @@ AMS_DEV void flush_place_stats(const Ws &w, const PlaceStats &ps) {
 }
 
 AMS_DEV void push_leaf(const Ws &w, Seg s, PlaceStats &ps) {
-  uint32_t slot = atomicAdd(&w.ctr->nleaf, 1u);
-  if (slot < w.capLeaf) w.leaves[slot] = s; else raise_error(w.ctr, 1u);
   const uint32_t kind = seg_kind(s.meta);
+  if (kind == LEAF_BIG) {
+    const uint32_t slot = atomicAdd(&w.ctr->nbl, 1u);
+    if (slot < w.capBig) w.bigLeaves[slot] = s; else raise_error(w.ctr, 1u);
+  } else {
+    const uint32_t slot = atomicAdd(&w.ctr->nleaf, 1u);
+    if (slot < w.capLeaf) w.leaves[slot] = s; else raise_error(w.ctr, 1u);
+  }
   ps.leafKeys[kind < 3 ? kind : 0] += s.size;
   ps.big += kind == LEAF_BIG ? 1u : 0u;
 }
@@ -2520,6 +2530,352 @@ AMS_DEV void wg_merge(const typename Key<KT>::T *A_, const uint32_t *vA_, uint32
   }
 }
 
+// Last resort for a range of n > C keys that the partition below could not
+// split into pieces of at most C: runs of C keys sorted in LDS, then pairs of
+// runs merged, ping-ponging between the range's TMP and OUT buffers so that
+// the last pass lands in OUT.  src may be either buffer (a run is read
+// completely before it is written).
+template <int KT, bool PAY>
+AMS_DEV void merge_fallback(const Ws &w, const Root &R, uint32_t off, uint32_t n,
+                            const typename Key<KT>::T *src, const uint32_t *vsrc, bool enc_in,
+                            const FinSmem<typename Key<KT>::T> &sm, uint32_t C, uint32_t cutoff,
+                            uint64_t seed, uint32_t root, bool sampled_only) {
+  typedef typename Key<KT>::T K;
+  if (threadIdx.x == 0) {
+    atomicAdd(&w.ctr->nmerge, 1u);
+    atomicAdd(&w.ctr->merge_keys, (unsigned long long)n);
+  }
+  const uint32_t runs = (n + C - 1) / C;
+  const uint32_t passes = ilog2c(runs);
+  K *bufK[2] = {kptr<K>(w, R, BUF_TMP) + off, kptr<K>(w, R, BUF_OUT) + off};
+  uint32_t *bufV[2] = {PAY ? vptr(w, R, BUF_TMP) + off : nullptr,
+                       PAY ? vptr(w, R, BUF_OUT) + off : nullptr};
+  uint32_t curb = (passes & 1u) ? 0u : 1u;  // run buffer: OUT after an even number of passes
+  for (uint32_t r = 0; r < runs; ++r) {
+    uint32_t o = r * C, sz = n - o < C ? n - o : C;
+    lds_sort<KT, PAY>(sm, src + o, PAY ? vsrc + o : nullptr, enc_in, bufK[curb] + o,
+                      PAY ? bufV[curb] + o : nullptr, passes == 0, sz, C, cutoff,
+                      stream_state(seed, LEAF_STREAM, root, off + o), sampled_only);
+  }
+  for (uint32_t pz = 0; pz < passes; ++pz) {
+    const uint32_t width = C << pz;
+    const uint32_t nxt = curb ^ 1u;
+    const bool last = pz + 1 == passes;
+    for (uint32_t a = 0; a < n; a += 2 * width) {
+      uint32_t na = n - a < width ? n - a : width;
+      uint32_t nb = n - a - na < width ? n - a - na : width;
+      wg_merge<KT, PAY>(bufK[curb] + a, PAY ? bufV[curb] + a : nullptr, na,
+                        bufK[curb] + a + na, PAY ? bufV[curb] + a + na : nullptr, nb,
+                        bufK[nxt] + a, PAY ? bufV[nxt] + a : nullptr, last);
+    }
+    __syncthreads();
+    curb = nxt;
+  }
+}
+
+// An oversized leaf (a group larger than the base case's capacity C after
+// the planned levels) gets one more partition level, in HBM, from the
+// workgroup that owns it (Section 6: groups are split again until they fit
+// a processor).  16 f keys at random positions are ranked in LDS; f - 1 of
+// them split the leaf into f buckets of about n / f <= C / 4 keys, with an
+// equality bucket after every splitter (Appendix D; 2f - 1 ids in key order).
+// A count pass and a stable scatter pass move the keys bucket by bucket into
+// the range's other buffer (TMP or OUT, the one the leaf is not in).  The
+// caller then sorts every bucket of at most C keys in LDS into OUT, copies
+// the equality buckets (their keys are equal) and hands a bucket still
+// larger than C on: it is partitioned once more, and what is still larger
+// than C after that goes to the merge fallback.
+constexpr uint32_t BIG_A = 16;         // samples per bucket
+constexpr uint32_t BIG_SAMPLE = 1024;  // sample room (BIG_A * BIG_FMAX)
+constexpr uint32_t BIG_FMAX = 64;          // buckets per partition
+constexpr uint32_t BIG_IDS = 2 * BIG_FMAX;  // ids (2f - 1 used), one counter each
+constexpr uint32_t BIG_RPT = 8;             // keys per thread and count or scatter chunk
+static_assert(BIG_A * BIG_FMAX <= BIG_SAMPLE, "the sample fits its LDS room");
+// LDS of the partition: sample, sorted sample, splitters, then the counters
+template <typename K> __host__ __device__ constexpr size_t big_smem_bytes() {
+  return (2 * BIG_SAMPLE + BIG_FMAX) * sizeof(K) +
+         (BIG_IDS + 1 + BIG_IDS + (FIN_THREADS / 64) * BIG_IDS) * sizeof(uint32_t);
+}
+
+// Returns the number of ids NB; lane l of every wavefront receives the
+// starts of buckets l and l + 64 in bs0 and bs1 (bucket_start), start NB
+// being the leaf's size.  The buckets sit in buffer sbuf of the leaf's range.
+template <int KT, bool PAY>
+AMS_DEV uint32_t big_partition(const Ws &w, const Root &R, const Seg &L, unsigned char *smem,
+                               uint32_t C, uint64_t seed, uint32_t sbuf, uint32_t &bs0,
+                               uint32_t &bs1) {
+  typedef typename Key<KT>::T K;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  constexpr uint32_t NW = FIN_THREADS / 64;
+  const uint32_t n = L.size, buf = seg_buf(L.meta);
+  const bool enc = buf == BUF_IN;
+  const GMem<K> *src = (const GMem<K> *)(kptr<K>(w, R, buf) + L.off);
+  const GMem<uint32_t> *vsrc = PAY ? (const GMem<uint32_t> *)(vptr(w, R, buf) + L.off) : nullptr;
+  K *stK_ = kptr<K>(w, R, sbuf) + L.off;
+  uint32_t *stV_ = PAY ? vptr(w, R, sbuf) + L.off : nullptr;
+  GMem<K> *stK = (GMem<K> *)stK_;
+  GMem<uint32_t> *stV = (GMem<uint32_t> *)stV_;
+  // LDS (the base case's layout is not in use until the buckets are sorted)
+  K *smp = (K *)smem;                       // BIG_SAMPLE sample keys
+  K *srt = smp + BIG_SAMPLE;                // the sample in order
+  K *spl = srt + BIG_SAMPLE;                // spl[1..f-1]: splitters
+  uint32_t *hist = (uint32_t *)(spl + BIG_FMAX);  // BIG_IDS + 1: counts, then starts
+  uint32_t *cur = hist + BIG_IDS + 1;             // BIG_IDS: next free slot per id
+  uint32_t *rows = cur + BIG_IDS;                 // NW x BIG_IDS: per-wave counts, then bases
+  // f: the smallest power of two with n / f <= C / 4 (at least 2, at most BIG_FMAX)
+  uint32_t f = 2;
+  while (f < BIG_FMAX && (uint64_t)f * (C / 4) < n) f <<= 1;
+  const uint32_t logf = ilog2c(f), NB = 2 * f - 1, S = BIG_A * f;
+  // ---- sample and splitters
+  const uint64_t st = stream_state(seed, LEAF_STREAM - 1, L.root, L.off);
+  for (uint32_t t = tid; t < S; t += FIN_THREADS) {
+    const K y = src[draw_pos(st, t, n)];
+    smp[t] = enc ? Key<KT>::enc(y) : y;
+  }
+  for (uint32_t q = tid; q < BIG_IDS + 1; q += FIN_THREADS) hist[q] = 0;
+  for (uint32_t q = tid; q < NW * BIG_IDS; q += FIN_THREADS) rows[q] = 0;
+  __syncthreads();
+  for (uint32_t t = tid; t < S; t += FIN_THREADS) {
+    // rank among all samples, ties broken by index (Section 4.2)
+    const K x = smp[t];
+    uint32_t r = 0;
+    for (uint32_t j = 0; j < S; ++j) {
+      const K y = smp[j];
+      r += (uint32_t)(y < x) | ((uint32_t)(y == x) & (uint32_t)(j < t));
+    }
+    srt[r] = x;
+  }
+  __syncthreads();
+  if (tid >= 1 && tid < f) spl[tid] = srt[BIG_A * tid - 1];
+  __syncthreads();
+  // id of x: 2b for the regular bucket b (b = splitters below x), 2b + 1 when
+  // x equals the splitter above it
+  auto classify_big = [&](K x) -> uint32_t {
+    uint32_t b = 0;
+    for (uint32_t half = f >> 1; half; half >>= 1)
+      if (b + half < f && spl[b + half] < x) b += half;
+    const bool eqb = b + 1 < f && spl[b + 1] == x;
+    return 2 * b + (eqb ? 1u : 0u);
+  };
+  // ---- count (BIG_RPT loads per thread in flight at a time)
+  for (uint32_t base = 0; base < n; base += FIN_THREADS * BIG_RPT) {
+    K xs[BIG_RPT];
+#pragma unroll
+    for (uint32_t k = 0; k < BIG_RPT; ++k) {
+      const uint32_t p = base + k * FIN_THREADS + tid;
+      xs[k] = p < n ? (K)src[p] : (K)0;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < BIG_RPT; ++k) {
+      if (base + k * FIN_THREADS + tid < n)
+        atomicAdd(&hist[classify_big(enc ? Key<KT>::enc(xs[k]) : xs[k])], 1u);
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {  // exclusive scan of the NB <= 127 counts, two per lane
+    const uint32_t c0 = 2 * lane < NB ? hist[2 * lane] : 0u;
+    const uint32_t c1 = 2 * lane + 1 < NB ? hist[2 * lane + 1] : 0u;
+    const uint32_t inc = wave_incl_scan(c0 + c1);
+    const uint32_t e = inc - c0 - c1;
+    if (2 * lane < NB) cur[2 * lane] = e;
+    if (2 * lane + 1 < NB) cur[2 * lane + 1] = e + c0;
+  }
+  __syncthreads();
+  for (uint32_t q = tid; q < NB; q += FIN_THREADS) hist[q] = cur[q];  // bucket starts
+  if (tid == 0) hist[NB] = n;
+  // ---- stable scatter: wavefront v takes the v-th eighth of each chunk of
+  // FIN_THREADS * BIG_RPT keys, as BIG_RPT rows of 64 keys in input order
+  for (uint32_t base = 0; base < n; base += FIN_THREADS * BIG_RPT) {
+    K xs[BIG_RPT];
+    uint32_t vs[BIG_RPT], ir[BIG_RPT];  // id << 16 | rank inside the wavefront's range
+#pragma unroll
+    for (uint32_t k = 0; k < BIG_RPT; ++k) {  // every load of the chunk first
+      const uint32_t p = base + (wave * BIG_RPT + k) * 64 + lane;
+      const bool valid = p < n;
+      xs[k] = valid ? (K)src[p] : (K)0;
+      vs[k] = (PAY && valid) ? (uint32_t)vsrc[p] : 0u;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < BIG_RPT; ++k) {
+      const uint32_t p = base + (wave * BIG_RPT + k) * 64 + lane;
+      const bool valid = p < n;
+      if (enc) xs[k] = Key<KT>::enc(xs[k]);
+      const K x = xs[k];
+      const uint32_t id = valid ? classify_big(x) : 0u;
+      const uint64_t peers = match_lanes(id, valid, logf + 1);
+      const uint32_t below = bits_below(peers);
+      uint32_t r = 0;
+      if (valid) {
+        uint32_t *c = rows + wave * BIG_IDS + id;
+        r = *c + below;
+        if (below == 0) *c = r + (uint32_t)__popcll(peers);
+      }
+      ir[k] = valid ? (id << 16) | r : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    if (tid < NB) {  // per id: wavefront bases in order, then the next free slot
+      uint32_t run = cur[tid];
+      for (uint32_t v = 0; v < NW; ++v) {
+        const uint32_t c = rows[v * BIG_IDS + tid];
+        rows[v * BIG_IDS + tid] = run;
+        run += c;
+      }
+      cur[tid] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < BIG_RPT; ++k) {
+      if (ir[k] != 0xFFFFFFFFu) {
+        const uint32_t d = rows[wave * BIG_IDS + (ir[k] >> 16)] + (ir[k] & 0xFFFFu);
+        stK[d] = xs[k];
+        if (PAY) stV[d] = vs[k];
+      }
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < NW * BIG_IDS; q += FIN_THREADS) rows[q] = 0;
+    __syncthreads();
+  }
+  // bucket starts into registers (the LDS is handed to the base case next)
+  bs0 = lane <= NB ? hist[lane] : n;
+  bs1 = lane + 64 <= NB ? hist[lane + 64] : n;
+  // the stores above must be complete before the buckets are read back
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  return NB;
+}
+
+AMS_DEV uint32_t bucket_start(uint32_t bs0, uint32_t bs1, uint32_t id) {
+  return id < 64 ? (uint32_t)__builtin_amdgcn_readlane((int)bs0, (int)id)
+                 : (uint32_t)__builtin_amdgcn_readlane((int)bs1, (int)(id - 64));
+}
+
+// Keys of an equality bucket are equal: copied in order (decoded).
+template <int KT, bool PAY>
+AMS_DEV void copy_range(const typename Key<KT>::T *src, const uint32_t *vsrc,
+                        typename Key<KT>::T *dst, uint32_t *vdst, uint32_t n) {
+  typedef typename Key<KT>::T K;
+  for (uint32_t q = threadIdx.x; q < n; q += FIN_THREADS) {
+    ((GMem<K> *)dst)[q] = Key<KT>::dec(((const GMem<K> *)src)[q]);
+    if (PAY) ((GMem<uint32_t> *)vdst)[q] = ((const GMem<uint32_t> *)vsrc)[q];
+  }
+}
+
+// Oversized leaves, before the base case: each is partitioned once more by one
+// workgroup (big_partition).  Its buckets join the leaf list that k_finish
+// sorts (regular buckets as leaves, equality buckets as copies, all of one
+// partition in one block of entries).  A regular bucket still larger than C,
+// and every bucket when the leaf list has no room left, goes to the
+// remainder list that k_big_rest finishes after the base case.  No base
+// case in this kernel: it needs little LDS and few registers, so many
+// workgroups partition side by side.
+template <int KT, bool PAY>
+__global__ void __launch_bounds__(FIN_THREADS, PAY ? 4 : 8) k_big_part(Ws w, uint32_t C, uint64_t seed,
+                                                             uint32_t flags) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ uint32_t sSlot;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  uint32_t nb = w.ctr->nbl;
+  if (nb > w.capBig) nb = w.capBig;
+  for (uint32_t li = blockIdx.x; li < nb; li += gridDim.x) {
+    const Seg L = w.bigLeaves[li];
+    const Root R = w.roots[L.root];
+    if ((uint64_t)L.off + L.size > R.n || seg_kind(L.meta) != LEAF_BIG) {
+      if (tid == 0) raise_error(w.ctr, 32u);
+      continue;
+    }
+    const uint32_t sbuf = seg_buf(L.meta) == BUF_OUT ? BUF_TMP : BUF_OUT;
+    uint32_t b0, b1;
+    const uint32_t NB = big_partition<KT, PAY>(w, R, L, smem_raw, C, seed, sbuf, b0, b1);
+    if (tid == 0) sSlot = atomicAdd(&w.ctr->nleaf, NB);
+    __syncthreads();
+    const uint32_t base = sSlot;
+    __syncthreads();
+    const bool room = (uint64_t)base + NB <= w.capLeaf && !(flags & AMS_FLAG_TEST_NO_PIECE_ROOM);
+    if (!room && tid == 0) {
+      // no room for its pieces: the whole leaf goes to the remainder list
+      const uint32_t r = atomicAdd(&w.ctr->nrest, 1u);
+      if (r < 2 * w.capBig) w.bigLeaves[w.capBig + r] = L; else raise_error(w.ctr, 1u);
+    }
+    if (tid < 64) {
+#pragma unroll
+      for (uint32_t h = 0; h < 2; ++h) {
+        const uint32_t id = lane + 64 * h;
+        // starts of buckets id and id + 1 (every lane takes part in the shuffles)
+        const uint32_t s0 = __shfl(b0, (int)(id & 63u), 64), s1 = __shfl(b1, (int)(id & 63u), 64);
+        const uint32_t n1 = (id + 1) & 63u;
+        const uint32_t e0 = __shfl(b0, (int)n1, 64), e1 = __shfl(b1, (int)n1, 64);
+        const uint32_t lo = id < 64 ? s0 : s1, hi = id + 1 < 64 ? e0 : e1;
+        if (id < NB) {
+          const bool eqb = (id & 1u) != 0;
+          const uint32_t sz = hi - lo;
+          const bool big = !eqb && sz > C;
+          const Seg piece{L.off + lo, sz, L.root,
+                          make_meta(sbuf, eqb ? LEAF_COPY : (big ? LEAF_BIG : LEAF_REG), 0, 0, 0)};
+          // every entry of the block that exists is written (an empty one
+          // for a piece that is finished elsewhere)
+          if (base + id < w.capLeaf)
+            w.leaves[base + id] = (room && !big) ? piece
+                                                 : Seg{L.off + lo, 0, L.root,
+                                                       make_meta(sbuf, LEAF_COPY, 0, 0, 0)};
+          if (room && big) {  // more than C keys: partitioned once more by k_big_rest
+            const uint32_t r = atomicAdd(&w.ctr->nrest, 1u);
+            if (r < 2 * w.capBig) w.bigLeaves[w.capBig + r] = piece; else raise_error(w.ctr, 1u);
+          }
+        }
+      }
+    }
+  }
+}
+
+// The remainder of the oversized leaves, after the base case (its list is
+// normally empty): buckets that one partition left larger than C, and
+// oversized leaves whose pieces found no room in the leaf list.  Each is
+// partitioned (once more); its buckets of at most C keys are sorted in LDS,
+// its equality buckets copied, and a bucket still larger than C is sorted by
+// the merge fallback.
+template <int KT, bool PAY>
+__global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_big_rest(Ws w, uint32_t C,
+                                                          uint32_t cutoff, uint64_t seed,
+                                                          uint32_t flags) {
+  const bool sampled_only = (flags & AMS_FLAG_SAMPLED_LEAF_SPLIT) != 0;
+  typedef typename Key<KT>::T K;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  FinSmem<K> sm = fin_smem<K, PAY>(smem_raw, C);
+  uint32_t nr = w.ctr->nrest;
+  if (nr > 2 * w.capBig) nr = 2 * w.capBig;
+  for (uint32_t li = blockIdx.x; li < nr; li += gridDim.x) {
+    const Seg L = w.bigLeaves[w.capBig + li];
+    const Root R = w.roots[L.root];
+    const uint32_t buf = seg_buf(L.meta);
+    if ((uint64_t)L.off + L.size > R.n || seg_kind(L.meta) != LEAF_BIG) {
+      if (threadIdx.x == 0) raise_error(w.ctr, 32u);
+      continue;
+    }
+    K *oK = (K *)R.kout + L.off;
+    uint32_t *oV = PAY ? R.vout + L.off : nullptr;
+    const uint32_t sbuf = buf == BUF_OUT ? BUF_TMP : BUF_OUT;
+    uint32_t b0, b1;
+    const uint32_t NB = big_partition<KT, PAY>(w, R, L, smem_raw, C, seed, sbuf, b0, b1);
+    K *bK = kptr<K>(w, R, sbuf) + L.off;
+    uint32_t *bV = PAY ? vptr(w, R, sbuf) + L.off : nullptr;
+    for (uint32_t id = 0; id < NB; ++id) {
+      const uint32_t lo = bucket_start(b0, b1, id), sz = bucket_start(b0, b1, id + 1) - lo;
+      if (sz == 0) continue;
+      if (id & 1u)
+        copy_range<KT, PAY>(bK + lo, PAY ? bV + lo : nullptr, oK + lo, PAY ? oV + lo : nullptr, sz);
+      else if (sz <= C)
+        lds_sort<KT, PAY>(sm, bK + lo, PAY ? bV + lo : nullptr, false, oK + lo,
+                          PAY ? oV + lo : nullptr, true, sz, C, cutoff,
+                          stream_state(seed, LEAF_STREAM, L.root, L.off + lo), sampled_only);
+      else
+        merge_fallback<KT, PAY>(w, R, L.off + lo, sz, bK + lo, PAY ? bV + lo : nullptr, false, sm,
+                                C, cutoff, seed, L.root, sampled_only);
+    }
+  }
+}
+
+// The base case over the leaf list (regular leaves, copies of final
+// children and the pieces of oversized leaves), one workgroup per leaf.
 template <int KT, bool PAY>
 __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint32_t C, uint32_t cutoff,
                                                         uint64_t seed, uint32_t flags) {
@@ -2533,59 +2889,22 @@ __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint3
   for (uint32_t li = blockIdx.x; li < nleaf; li += gridDim.x) {
     const Seg L = w.leaves[li];
     const Root R = w.roots[L.root];
-    if ((uint64_t)L.off + L.size > R.n) {  // defensive: never touch memory outside the root
+    const uint32_t kind = seg_kind(L.meta), buf = seg_buf(L.meta);
+    // defensive: never touch memory outside the root, nor more than C keys
+    if ((uint64_t)L.off + L.size > R.n || (kind == LEAF_REG && L.size > C) || kind == LEAF_BIG) {
       if (tid == 0) raise_error(w.ctr, 32u);
       continue;
     }
-    const uint32_t kind = seg_kind(L.meta), buf = seg_buf(L.meta);
     const K *src = kptr<K>(w, R, buf) + L.off;
     const uint32_t *vsrc = PAY ? vptr(w, R, buf) + L.off : nullptr;
     K *dst = (K *)R.kout + L.off;
     uint32_t *vdst = PAY ? R.vout + L.off : nullptr;
     if (kind == LEAF_COPY) {
-      for (uint32_t q = tid; q < L.size; q += FIN_THREADS) {
-        ((GMem<K> *)dst)[q] = Key<KT>::dec(((const GMem<K> *)src)[q]);
-        if (PAY) ((GMem<uint32_t> *)vdst)[q] = ((const GMem<uint32_t> *)vsrc)[q];
-      }
+      copy_range<KT, PAY>(src, vsrc, dst, vdst, L.size);
       continue;
     }
-    const uint64_t st = stream_state(seed, LEAF_STREAM, L.root, L.off);
-    if (kind == LEAF_REG) {
-      lds_sort<KT, PAY>(sm, src, vsrc, buf == BUF_IN, dst, vdst, true, L.size, C, cutoff, st,
-                        sampled_only);
-      continue;
-    }
-    // Oversized leaf (a group larger than LDS after the planned levels):
-    // sort runs of C keys in LDS, then merge pairs of runs, ping-ponging
-    // between this range of the TMP and OUT buffers so the last pass lands
-    // in OUT.
-    const uint32_t n = L.size;
-    const uint32_t runs = (n + C - 1) / C;
-    const uint32_t passes = ilog2c(runs);
-    K *bufK[2] = {kptr<K>(w, R, BUF_TMP) + L.off, kptr<K>(w, R, BUF_OUT) + L.off};
-    uint32_t *bufV[2] = {PAY ? vptr(w, R, BUF_TMP) + L.off : nullptr,
-                         PAY ? vptr(w, R, BUF_OUT) + L.off : nullptr};
-    uint32_t curb = (passes & 1u) ? 0u : 1u;  // run buffer: OUT after an even number of passes
-    for (uint32_t r = 0; r < runs; ++r) {
-      uint32_t o = r * C, sz = n - o < C ? n - o : C;
-      lds_sort<KT, PAY>(sm, src + o, PAY ? vsrc + o : nullptr, buf == BUF_IN, bufK[curb] + o,
-                        PAY ? bufV[curb] + o : nullptr, false, sz, C, cutoff,
-                        stream_state(seed, LEAF_STREAM, L.root, L.off + o), sampled_only);
-    }
-    for (uint32_t pz = 0; pz < passes; ++pz) {
-      const uint32_t width = C << pz;
-      const uint32_t nxt = curb ^ 1u;
-      const bool last = pz + 1 == passes;
-      for (uint32_t a = 0; a < n; a += 2 * width) {
-        uint32_t na = n - a < width ? n - a : width;
-        uint32_t nb = n - a - na < width ? n - a - na : width;
-        wg_merge<KT, PAY>(bufK[curb] + a, PAY ? bufV[curb] + a : nullptr, na,
-                          bufK[curb] + a + na, PAY ? bufV[curb] + a + na : nullptr, nb,
-                          bufK[nxt] + a, PAY ? bufV[nxt] + a : nullptr, last);
-      }
-      __syncthreads();
-      curb = nxt;
-    }
+    lds_sort<KT, PAY>(sm, src, vsrc, buf == BUF_IN, dst, vdst, true, L.size, C, cutoff,
+                      stream_state(seed, LEAF_STREAM, L.root, L.off), sampled_only);
   }
 }
 
@@ -2835,6 +3154,8 @@ ams_status run_stats(const void *ws, hipStream_t s, ams_run_stats *out) {
   out->leaf_keys = c.leaf_keys[LEAF_REG];
   out->copy_keys = c.leaf_keys[LEAF_COPY];
   out->big_keys = c.leaf_keys[LEAF_BIG];
+  out->merge_ranges = c.nmerge;
+  out->merge_keys = c.merge_keys;
   return AMS_OK;
 }
 
@@ -2976,9 +3297,14 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     uint64_t nextP = std::min<uint64_t>(P * ls.CH, keys / (C + 1));
     P = nextP;
   }
-  pl.capLeaf = (uint32_t)std::min<uint64_t>(leaves + total / C + 2, 0xFFFFFFF0ull);
+  // leaves, plus room for the pieces of oversized leaves (2 * BIG_FMAX - 1
+  // per partition; more pieces than that are finished by their partitioner)
+  pl.capLeaf = (uint32_t)std::min<uint64_t>(leaves + total / C + 2 + 2 * BIG_FMAX * 1024ull,
+                                            0xFFFFFFF0ull);
   // test hook: a leaf table of one entry, so that a sort needing more leaves
   // takes the device's table-overflow path (raises AMS_DEVERR_TABLE)
+  // an oversized leaf holds more than C keys
+  pl.capBig = (uint32_t)std::min<uint64_t>(total / (C + 1) + nroots + 2, 0xFFFFFFF0ull);
   if (pl.flags & AMS_FLAG_TEST_TINY_TABLES) pl.capLeaf = 1;
   uint32_t capAct = 1, capTile = 1, capBlk = 1, capS = 1, maxHS = 2, maxCH = 3, maxM = 2, maxS = 256;
   for (uint32_t l = 0; l < L; ++l) {
@@ -3015,6 +3341,7 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
   for (uint32_t l = 0; l <= MAXLEV; ++l)
     pl.o_act[l] = take(l < L ? (size_t)pl.lev[l].P * sizeof(Seg) : 0);
   pl.o_leaves = take((size_t)pl.capLeaf * sizeof(Seg));
+  pl.o_big = take((size_t)pl.capBig * 3 * sizeof(Seg));  // oversized leaves, then the remainder
   const bool any = L > 0;
   // per-subproblem and per-tile tables: the kernels index them with the
   // level's own strides, so each holds the largest level's rows
@@ -3072,6 +3399,8 @@ static Ws carve(const Plan &pl, char *base) {
   }
   w.leaves = (Seg *)(base + pl.o_leaves);
   w.capLeaf = pl.capLeaf;
+  w.bigLeaves = (Seg *)(base + pl.o_big);
+  w.capBig = pl.capBig;
   w.tileStart = (uint32_t *)(base + pl.o_tileStart);
   w.blkStart = (uint32_t *)(base + pl.o_blkStart);
   w.sampStart = (uint32_t *)(base + pl.o_sampStart);
@@ -3282,11 +3611,26 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
     }
   }
   if (!dbg_hist) {
-    size_t ldsF = fin_smem_bytes<K, PAY>(pl.C);
+    const size_t ldsF = fin_smem_bytes<K, PAY>(pl.C);
+    if (pl.L > 0) {
+      allow_lds(k_big_part<KT, PAY>, big_smem_bytes<K>());
+      TraceScope ts("big_part", 0xFFFFFFFFu, s);
+      hipLaunchKernelGGL((k_big_part<KT, PAY>), dim3(grid_for(pl.capBig, 1024)), dim3(FIN_THREADS),
+                         big_smem_bytes<K>(), s, w, pl.C, pl.seed, pl.flags);
+    }
     allow_lds(k_finish<KT, PAY>, ldsF);
-    TraceScope ts("finish", 0xFFFFFFFFu, s);
-    hipLaunchKernelGGL((k_finish<KT, PAY>), dim3(grid_for(pl.capLeaf, PAY ? 256 : 512)),
-                       dim3(FIN_THREADS), ldsF, s, w, pl.C, pl.cutoff, pl.seed, pl.flags);
+    {
+      TraceScope ts("finish", 0xFFFFFFFFu, s);
+      hipLaunchKernelGGL((k_finish<KT, PAY>), dim3(grid_for(pl.capLeaf, PAY ? 256 : 512)),
+                         dim3(FIN_THREADS), ldsF, s, w, pl.C, pl.cutoff, pl.seed, pl.flags);
+    }
+    if (pl.L > 0) {
+      const size_t ldsR = std::max(ldsF, big_smem_bytes<K>());
+      allow_lds(k_big_rest<KT, PAY>, ldsR);
+      TraceScope ts("big_rest", 0xFFFFFFFFu, s);
+      hipLaunchKernelGGL((k_big_rest<KT, PAY>), dim3(grid_for(pl.capBig, PAY ? 256 : 512)),
+                         dim3(FIN_THREADS), ldsR, s, w, pl.C, pl.cutoff, pl.seed, pl.flags);
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {

@@ -1,5 +1,5 @@
-"""GPU parity of the batched sort, of deep and forced level plans, and of the
-oversized-group fallback."""
+"""GPU parity of the batched sort, of deep and forced level plans, and of
+oversized groups (partitioned once more, merged only beyond that)."""
 
 import numpy as np
 import pytest
@@ -89,24 +89,124 @@ def test_forced_level_plans(api, kt, levels, k, b):
     assert np.array_equal(out, want)
 
 
+def _sort_with_stats(api, kt, keys, p, vals=None, offsets=None):
+    """Sort through the C ABI in a workspace of our own; (keys, vals, stats)."""
+    n = keys.size
+    if offsets is None:
+        ws = api.alloc_workspace(api.workspace_bytes(kt, n, vals is not None, p))
+        if vals is None:
+            return to_host(api.sort_keys(to_dev(keys), params=p, workspace=ws)), None, \
+                api.workspace_stats(ws)
+        ok, ov = api.sort_pairs(to_dev(keys), to_dev(vals), params=p, workspace=ws)
+        return to_host(ok), to_host(ov), api.workspace_stats(ws)
+    ws = api.alloc_workspace(api.batch_workspace_bytes(kt, offsets, vals is not None, p))
+    if vals is None:
+        return to_host(api.sort_batch(to_dev(keys), offsets, params=p, workspace=ws)), None, \
+            api.workspace_stats(ws)
+    ok, ov = api.sort_batch(to_dev(keys), offsets, vals=to_dev(vals), params=p, workspace=ws)
+    return to_host(ok), to_host(ov), api.workspace_stats(ws)
+
+
+# Oversized groups (more keys than a leaf holds once the planned levels are
+# done) are partitioned once more in HBM by their workgroup, into buckets of
+# about a quarter of a leaf; only a bucket still larger than a leaf is merged.
+@pytest.mark.parametrize("kt", [U64, U32, F32])
 @pytest.mark.parametrize("pairs", [False, True])
-@pytest.mark.parametrize("dist", ["uniform", "few"])
-def test_oversized_groups_take_the_merge_fallback(api, pairs, dist):
+@pytest.mark.parametrize("dist", ["uniform", "few", "zipf", "sorted"])
+def test_oversized_groups_partitioned(api, kt, pairs, dist):
     # one level of 4 groups over 100000 keys with 1024-key leaves: every
-    # group is far larger than a leaf, so the base case merges sorted runs
+    # group holds about 25000 keys, 64 buckets of about 400 each
     n = 100000
-    keys = gen(U64, n, dist, 60)
+    keys = gen(kt, n, dist, 60)
+    vals = np.arange(n, dtype=np.uint32) if pairs else None
     p = api.make_params(levels=1, k=4, overpartition_b=1, leaf_capacity=1024)
-    log("fallback pairs=%s %s" % (pairs, dist))
+    log("oversized groups kt=%d pairs=%s %s" % (kt, pairs, dist))
+    ok, ov, st = _sort_with_stats(api, kt, keys, p, vals)
+    wk, wv = oracle.oracle_sort(kt, keys, vals)
+    assert np.array_equal(ok.view(np.uint8), wk.view(np.uint8))
     if pairs:
-        vals = np.arange(n, dtype=np.uint32)
-        ok, ov = api.sort_pairs(to_dev(keys), to_dev(vals), params=p)
-        wk, wv = oracle.oracle_sort(U64, keys, vals)
-        assert np.array_equal(to_host(ok), wk) and np.array_equal(to_host(ov), wv)
-    else:
-        out = to_host(api.sort_keys(to_dev(keys), params=p))
-        want, _ = oracle.oracle_sort(U64, keys)
-        assert np.array_equal(out, want)
+        assert np.array_equal(ov, wv)
+    assert st["device_errors"] == 0
+    if dist != "few":  # few distinct keys: the level's equality buckets take them
+        assert st["big_leaves"] >= 1 and st["big_keys"] > 0
+    if dist == "uniform":
+        assert st["merge_ranges"] == 0, st
+
+
+@pytest.mark.parametrize("kt", [U64, F32])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_oversized_group_pieces_without_room(api, kt, pairs):
+    # the pieces find the leaf list full (test hook): the remainder pass
+    # after the base case sorts and copies them instead
+    n = 100000
+    keys = gen(kt, n, "zipf", 65)
+    vals = np.arange(n, dtype=np.uint32) if pairs else None
+    p = api.make_params(levels=1, k=4, overpartition_b=1, leaf_capacity=1024, flags=64)
+    log("oversized pieces without room kt=%d pairs=%s" % (kt, pairs))
+    ok, ov, st = _sort_with_stats(api, kt, keys, p, vals)
+    wk, wv = oracle.oracle_sort(kt, keys, vals)
+    assert np.array_equal(ok.view(np.uint8), wk.view(np.uint8))
+    if pairs:
+        assert np.array_equal(ov, wv)
+    assert st["big_leaves"] >= 1 and st["device_errors"] == 0, st
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_oversized_groups_partitioned_twice(api, pairs):
+    # groups of 2^20 keys with 1024-key leaves: the first partition leaves 64
+    # buckets of about 16384 keys, each partitioned once more into pieces
+    # that fit a leaf; nothing is merged
+    n = 1 << 21
+    keys = gen(U64, n, "uniform", 61)
+    vals = np.arange(n, dtype=np.uint32) if pairs else None
+    p = api.make_params(levels=1, k=2, overpartition_b=1, leaf_capacity=1024)
+    log("oversized groups partitioned twice pairs=%s" % pairs)
+    ok, ov, st = _sort_with_stats(api, U64, keys, p, vals)
+    wk, wv = oracle.oracle_sort(U64, keys, vals)
+    assert np.array_equal(ok, wk)
+    if pairs:
+        assert np.array_equal(ov, wv)
+    assert st["big_leaves"] == 2 and st["merge_ranges"] == 0 and st["device_errors"] == 0, st
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_oversized_groups_beyond_two_partitions_merge(api, pairs):
+    # groups of 2^23 keys with 1024-key leaves: two partitions of 64 buckets
+    # leave pieces of about 2048 keys, which the merge fallback sorts
+    n = 1 << 24
+    keys = gen(U64, n, "uniform", 64)
+    vals = np.arange(n, dtype=np.uint32) if pairs else None
+    p = api.make_params(levels=1, k=2, overpartition_b=1, leaf_capacity=1024)
+    log("oversized groups beyond two partitions pairs=%s" % pairs)
+    ok, ov, st = _sort_with_stats(api, U64, keys, p, vals)
+    wk, wv = oracle.oracle_sort(U64, keys, vals)
+    assert np.array_equal(ok, wk)
+    if pairs:
+        assert np.array_equal(ov, wv)
+    assert st["big_leaves"] == 2 and st["merge_ranges"] > 64 and st["device_errors"] == 0, st
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_oversized_groups_in_a_skewed_batch(api, pairs):
+    # a few large segments among many small ones, 2048-key leaves, one level:
+    # the large segments' groups are oversized, the small ones fit a leaf
+    rng = np.random.default_rng(62)
+    sizes = rng.integers(1, 3000, 200).astype(np.int64)
+    sizes[[3, 50, 51, 120]] = [400000, 250000, 123457, 300001]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    n = int(offs[-1])
+    keys = gen(U64, n, "zipf", 63)
+    vals = np.arange(n, dtype=np.uint32) if pairs else None
+    p = api.make_params(levels=1, k=8, leaf_capacity=2048)
+    log("skewed batch pairs=%s n=%d" % (pairs, n))
+    ok, ov, st = _sort_with_stats(api, U64, keys, p, vals, offsets=offs)
+    for i in range(sizes.size):
+        a, b = int(offs[i]), int(offs[i + 1])
+        wk, wv = oracle.oracle_sort(U64, keys[a:b], None if vals is None else vals[a:b])
+        assert np.array_equal(ok[a:b], wk), i
+        if pairs:
+            assert np.array_equal(ov[a:b], wv), i
+    assert st["big_leaves"] >= 4 and st["device_errors"] == 0, st
 
 
 def test_workspace_given_by_caller(api):
