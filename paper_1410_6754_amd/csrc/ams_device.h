@@ -113,6 +113,7 @@ template <typename T> using GMem = __attribute__((address_space(1))) T;
 typedef uint64_t __attribute__((__may_alias__)) u64_alias;
 
 typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 
 AMS_DEV Rsrc make_rsrc(const void *base, uint32_t bytes) {
@@ -139,6 +140,18 @@ template <> struct Vec16<uint32_t> {
     x[3] = v.w;
   }
 };
+
+// One element (4 or 8 bytes) through a buffer resource at byte offset off
+// (the whole offset in the range-checked vector operand): past the
+// resource's range it reads as zero, so a load needs no branch.
+template <typename T> AMS_DEV T buf_load(Rsrc rs, uint32_t off);
+template <> AMS_DEV uint32_t buf_load<uint32_t>(Rsrc rs, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+}
+template <> AMS_DEV uint64_t buf_load<uint64_t>(Rsrc rs, uint32_t off) {
+  const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+  return ((uint64_t)v.y << 32) | v.x;
+}
 
 // Wave-uniform copy of a pointer (scalar registers).
 template <typename T> AMS_DEV T *uniform_ptr(T *p) {
@@ -231,29 +244,13 @@ template <typename T> AMS_DEV T wave_min(T v) {
 // ---------------------------------------------------------------------------
 AMS_DEV uint32_t eytzinger_slot(uint32_t j, uint32_t m) { return (m + j) >> (__builtin_ctz(j) + 1); }
 
-template <typename K> AMS_DEV uint32_t tree_descend(K x, const K *tree, uint32_t logm) {
-  uint32_t i = 1;
-  for (uint32_t l = 0; l < logm; ++l) i = 2 * i + (x > tree[i] ? 1u : 0u);
-  return i - (1u << logm);
-}
-
-// Bucket id: b = #{splitters < x}; with equality buckets, keys equal to the
-// splitter just above (sorted spl[b], b < m-1) get id 2b+1, others 2b.
-template <typename K>
-AMS_DEV uint32_t classify_id(K x, const K *tree, const K *spl, uint32_t logm, bool eq) {
-  uint32_t b = tree_descend(x, tree, logm);
-  if (!eq) return b;
-  uint32_t m = 1u << logm;
-  bool has_upper = b < m - 1;
-  K up = spl[has_upper ? b : 0];
-  return 2 * b + ((has_upper && x == up) ? 1u : 0u);
-}
-
 // Bucket ids of U keys at once: the descents advance level by level, so each
-// level issues U independent LDS reads.
+// level issues U independent LDS reads.  With equality buckets, the splitter
+// just above bucket b (in-order rank b + 1) is read from the tree itself
+// (eytzinger_slot), so classification touches no memory but the tree.
 template <typename K, int U>
-AMS_DEV void classify_batch(const K (&x)[U], uint32_t (&id)[U], const K *tree, const K *spl,
-                            uint32_t logm, bool eq) {
+AMS_DEV void classify_batch(const K (&x)[U], uint32_t (&id)[U], const K *tree, uint32_t logm,
+                            bool eq) {
   uint32_t i[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) i[u] = 1;
@@ -274,7 +271,7 @@ AMS_DEV void classify_batch(const K (&x)[U], uint32_t (&id)[U], const K *tree, c
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const uint32_t b = i[u] - m;
-    up[u] = spl[b < m - 1 ? b : 0];
+    up[u] = tree[b < m - 1 ? eytzinger_slot(b + 1, m) : 1u];
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {

@@ -559,8 +559,7 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
   constexpr int CU = 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   K *sTree = (K *)smem_raw;
-  K *sSpl = sTree + lv.mmax;
-  uint32_t *sH = (uint32_t *)(sSpl + lv.mmax);  // NB
+  uint32_t *sH = (uint32_t *)(sTree + lv.mmax);  // NB
   const uint32_t tid = threadIdx.x;
   const uint32_t P = w.ctr->P;
   ItemRange ir = xcd_items(w.ctr->ntile);
@@ -575,7 +574,7 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
       __syncthreads();
       logm = meta_logm(s.meta);
       m = 1u << logm;
-      eq = load_tree<K>(w, lv, i, m, sTree, sSpl);
+      eq = load_tree<K>(w, lv, i, m, sTree, nullptr);
       cur = i;
     }
     const uint32_t NB = eq ? 2 * m - 1 : m;
@@ -604,7 +603,7 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
         for (int u = 0; u < CU; ++u) xs[u] = Key<KT>::enc(xs[u]);
       }
       uint32_t ids[CU];
-      classify_batch<K, CU>(xs, ids, sTree, sSpl, logm, eq);
+      classify_batch<K, CU>(xs, ids, sTree, logm, eq);
       // one add for the whole wavefront when all its keys share a bucket
       // (sorted or skewed input), else one LDS atomic per key
       const uint32_t ntv = base + 256u * CU <= hi ? 256u * CU : hi - base;  // valid keys
@@ -1224,7 +1223,6 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
   ItemRange ir = xcd_items(w.ctr->ntile);
   uint32_t cur = 0xFFFFFFFFu, logm = 0, nch = 0, nbits = 0;
   bool eq = false;
-  const K *gSpl = nullptr;
   for (uint32_t g = ir.first; g < ir.end; g += ir.step) {
     uint32_t i = find_owner(w.tileStart, P, g);
     uint32_t t = g - w.tileStart[i];
@@ -1243,7 +1241,6 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
       for (uint32_t j = tid; j < NB; j += 256) sI2C[j] = gi[j];
       const uint8_t *gd = w.cdst + (size_t)i * CH;
       for (uint32_t c = tid; c < nch; c += 256) sCd[c] = gd[c];
-      gSpl = (const K *)w.spl + (size_t)i * lv.mmax;
       cur = i;
     }
     for (uint32_t c = tid; c < nch; c += 256) sBase[c] = w.tileOff[(size_t)g * CH + c];
@@ -1279,7 +1276,7 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
         for (int k = 0; k < KPT; ++k) xk[k] = Key<KT>::enc(xk[k]);
       }
       uint32_t xcr[KPT];  // child << 16 | rank inside (wave, child)
-      classify_batch<K, KPT>(xk, xcr, sTree, gSpl, logm, eq);
+      classify_batch<K, KPT>(xk, xcr, sTree, logm, eq);
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
         const uint32_t p = cb + wave * (CHK / 4) + k * 64 + lane;
@@ -1455,7 +1452,6 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
   ItemRange ir = xcd_items(w.ctr->ntile);
   uint32_t cur = 0xFFFFFFFFu, logm = 0, nch = 0;
   bool eq = false;
-  const K *gSpl = nullptr;
   if (PRIV) {
     for (uint32_t c = tid; c < 2 * SCK_PCH; c += SCK_THREADS) sCnt2[c] = 0;
   } else {
@@ -1492,7 +1488,6 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
       for (uint32_t j = tid; j < NB; j += SCK_THREADS) sI2C[j] = gi[j];
       const uint8_t *gd = w.cdst + (size_t)i * CH;
       for (uint32_t c = tid; c < nch; c += SCK_THREADS) sCd[c] = gd[c];
-      gSpl = (const K *)w.spl + (size_t)i * lv.mmax;
       cur = i;
       __syncthreads();  // the subproblem's tables are in LDS
     }
@@ -1508,7 +1503,7 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
         for (int k = 0; k < KPT; ++k) xa[k] = Key<KT>::enc(xa[k]);
       }
       uint32_t xcs[KPT];  // child << 16 | slot
-      classify_batch<K, KPT>(xa, xcs, sTree, gSpl, logm, eq);
+      classify_batch<K, KPT>(xa, xcs, sTree, logm, eq);
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
         const uint32_t p = cb + sck_pos<K, KPT>(k);
@@ -1639,7 +1634,6 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_pairs(Ws w, Lev lv) 
   ItemRange ir = xcd_items(w.ctr->ntile);
   uint32_t cur = 0xFFFFFFFFu, logm = 0, nch = 0, nbits = 0;
   bool eq = false;
-  const K *gSpl = nullptr;
   for (uint32_t q = tid; q < NW * CHP; q += SCK_THREADS) sRow[q] = 0;
   uint16_t *row = sRow + wave * CHP;
   for (uint32_t g = ir.first; g < ir.end; g += ir.step) {
@@ -1661,7 +1655,6 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_pairs(Ws w, Lev lv) 
       for (uint32_t j = tid; j < NB; j += SCK_THREADS) sI2C[j] = gi[j];
       const uint8_t *gd = w.cdst + (size_t)i * CH;
       for (uint32_t c = tid; c < nch; c += SCK_THREADS) sCd[c] = gd[c];
-      gSpl = (const K *)w.spl + (size_t)i * lv.mmax;
       cur = i;
       __syncthreads();  // the subproblem's tables are in LDS
     }
@@ -1671,16 +1664,29 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_pairs(Ws w, Lev lv) 
     const uint32_t buf = seg_buf(s.meta);
     const GMem<K> *src = (const GMem<K> *)(kptr<K>(w, R, buf) + s.off);
     const GMem<uint32_t> *vsrc = (const GMem<uint32_t> *)(vptr(w, R, buf) + s.off);
+    // the tile's constants in scalar registers (they stay live across the
+    // whole chunk loop)
+    GMem<K> *kTmp = (GMem<K> *)uniform_ptr(kptr<K>(w, R, BUF_TMP));
+    GMem<K> *kOut = (GMem<K> *)uniform_ptr(kptr<K>(w, R, BUF_OUT));
+    GMem<uint32_t> *vTmp = (GMem<uint32_t> *)uniform_ptr(vptr(w, R, BUF_TMP));
+    GMem<uint32_t> *vOut = (GMem<uint32_t> *)uniform_ptr(vptr(w, R, BUF_OUT));
     const bool enc = buf == BUF_IN;
-    const uint32_t lo = t * lv.TC;
-    const uint32_t hi = lo + lv.TC < s.size ? lo + lv.TC : s.size;
+    const uint32_t sOff = __builtin_amdgcn_readfirstlane(s.off);
+    const uint32_t sSize = __builtin_amdgcn_readfirstlane(s.size);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(t * lv.TC);
+    const uint32_t hi = lo + lv.TC < sSize ? lo + lv.TC : sSize;
     // keys are requested one chunk ahead; payloads at the start of their
-    // own chunk (they are needed only when the chunk is staged)
+    // own chunk (they are needed only when the chunk is staged).  Both go
+    // through buffer resources over the tile, whose range check returns
+    // zeros past its end: the loads need no branches, so the waits for
+    // them count exactly and the next chunk's keys stay in flight.
+    const Rsrc rk = make_rsrc(uniform_ptr((const K *)src + lo), (hi - lo) * (uint32_t)sizeof(K));
+    const Rsrc rv = make_rsrc(uniform_ptr((const uint32_t *)vsrc + lo), (hi - lo) * 4u);
     auto load_keys = [&](uint32_t cb, K (&xk)[KPT]) {
 #pragma unroll
       for (uint32_t k = 0; k < KPT; ++k) {
-        const uint32_t p = cb + wave * PW + k * 64 + lane;
-        xk[k] = p < hi ? src[p] : (K)0;
+        const uint32_t p = cb - lo + wave * PW + k * 64 + lane;
+        xk[k] = buf_load<K>(rk, p * (uint32_t)sizeof(K));
       }
     };
     K xk[KPT];
@@ -1689,17 +1695,17 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_pairs(Ws w, Lev lv) 
       uint32_t xv[KPT];
 #pragma unroll
       for (uint32_t k = 0; k < KPT; ++k) {
-        const uint32_t p = cb + wave * PW + k * 64 + lane;
-        xv[k] = p < hi ? vsrc[p] : 0u;
+        const uint32_t p = cb - lo + wave * PW + k * 64 + lane;
+        xv[k] = buf_load<uint32_t>(rv, p * 4u);
       }
       K nk[KPT];
-      if (cb + CHK < hi) load_keys(cb + CHK, nk);
+      load_keys(cb + CHK, nk);  // past the tile's end: zeros
       if (enc) {
 #pragma unroll
         for (uint32_t k = 0; k < KPT; ++k) xk[k] = Key<KT>::enc(xk[k]);
       }
       uint32_t xcr[KPT];  // child << 16 | rank among the wavefront's pairs of that child
-      classify_batch<K, KPT>(xk, xcr, sTree, gSpl, logm, eq);
+      classify_batch<K, KPT>(xk, xcr, sTree, logm, eq);
 #pragma unroll
       for (uint32_t k = 0; k < KPT; ++k) {
         const bool valid = cb + wave * PW + k * 64 + lane < hi;
@@ -1732,8 +1738,8 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_pairs(Ws w, Lev lv) 
           sRow[v * CHP + c] = (uint16_t)run;
           run += n;
         }
-        if ((uint64_t)sBase[c] + tot <= s.size) {
-          sRel[c] = s.off + sBase[c] - sL[c];
+        if ((uint64_t)sBase[c] + tot <= sSize) {
+          sRel[c] = sOff + sBase[c] - sL[c];
         } else {  // would overrun the subproblem: dropped and flagged
           raise_error(w.ctr, 16u);
           sRel[c] = 0xFFFFFFFFu;
@@ -1756,8 +1762,9 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_pairs(Ws w, Lev lv) 
       for (uint32_t j = lane; j < CHP / 4; j += 64) ((u64_alias *)row)[j] = 0;
       __syncthreads();
       // write out: consecutive slots of a child go to consecutive indices
+      // (a child's destination is the TMP or the OUT buffer, both uniform)
       const uint32_t cnt = hi - cb < CHK ? hi - cb : CHK;
-#pragma unroll
+#pragma unroll 2
       for (uint32_t k = 0; k < KPT; ++k) {
         const uint32_t q = tid + SCK_THREADS * k;
         if (q < cnt) {
@@ -1765,11 +1772,11 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_pairs(Ws w, Lev lv) 
           const uint32_t rel = sRel[cc];
           if (rel != 0xFFFFFFFFu) {
             const uint32_t cd = sCd[cc];
-            const uint32_t db = cd & 15u;
+            const bool toOut = (cd & 15u) == BUF_OUT;
             K x = stK[q];
             if (cd >> 4) x = Key<KT>::dec(x);
-            ((GMem<K> *)kptr<K>(w, R, db))[rel + q] = x;
-            ((GMem<uint32_t> *)vptr(w, R, db))[rel + q] = stV[q];
+            (toOut ? kOut : kTmp)[rel + q] = x;
+            (toOut ? vOut : vTmp)[rel + q] = stV[q];
           }
         }
       }
@@ -1854,7 +1861,7 @@ __host__ inline uint32_t fin_capacity(uint32_t kw, bool pay) {
 
 // classify FIN_KPT keys in two batches of half the width (register pressure)
 template <typename K>
-AMS_DEV void classify_halves(K (&x)[FIN_KPT], uint32_t (&id)[FIN_KPT], const K *tree, const K *spl,
+AMS_DEV void classify_halves(K (&x)[FIN_KPT], uint32_t (&id)[FIN_KPT], const K *tree,
                              uint32_t logf, bool eq, uint32_t s) {
   constexpr int H = FIN_KPT / 2;
   K xa[H];
@@ -1868,7 +1875,7 @@ AMS_DEV void classify_halves(K (&x)[FIN_KPT], uint32_t (&id)[FIN_KPT], const K *
     }
 #pragma unroll
     for (int u = 0; u < H; ++u) xa[u] = x[h * H + u];
-    classify_batch<K, H>(xa, ia, tree, spl, logf, eq);
+    classify_batch<K, H>(xa, ia, tree, logf, eq);
 #pragma unroll
     for (int u = 0; u < H; ++u) id[h * H + u] = ia[u];
   }
@@ -1961,7 +1968,6 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   static_assert(nwb <= 2 * FMAX, "the bitmap lives in the bucket-counter area");
   static_assert(2 * FMAX == FIN_THREADS, "one bucket counter per thread");
   if (!PAY) sm.cnt[tid] = 0;  // keys-only bucket counters (the previous call ended on a barrier)
-  const K *spl = sm.srt + 1;  // spl[b] = splitter just above bucket b
   K xk[FIN_KPT];
   uint32_t xv[FIN_KPT];
   uint32_t xir[FIN_KPT];  // id << 16 | slot
@@ -2193,7 +2199,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       dup = tid + 1 < f && sm.srt[tid] == sm.srt[tid + 1];
     }
     eq = __syncthreads_or(dup ? 1 : 0) != 0;
-    classify_halves<K>(xk, xir, sm.tree, spl, logf, eq, s);
+    classify_halves<K>(xk, xir, sm.tree, logf, eq, s);
     NB = eq ? 2 * f - 1 : f;
     Lb = count_scan(NB);
   } else if (f == 1) {
@@ -3521,7 +3527,7 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
                            dim3(256), lds, s, w, lv);
       }
     }
-    size_t ldsC = 2 * (size_t)ls.mmax * sizeof(K) + (size_t)ls.HS * 4;
+    size_t ldsC = (size_t)ls.mmax * sizeof(K) + (size_t)ls.HS * 4;
     allow_lds(k_count<KT>, ldsC);
     {
       TraceScope ts("count", l, s);
