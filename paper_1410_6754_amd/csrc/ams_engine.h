@@ -58,7 +58,7 @@ struct Plan {
   uint32_t capLeaf;
   uint32_t capBig;  // oversized-leaf list
   // workspace layout (byte offsets)
-  size_t o_tmpK, o_tmpV, o_roots, o_ctr, o_act[MAXLEV + 1], o_leaves, o_big, o_tileStart, o_blkStart,
+  size_t o_tmpK, o_tmpV, o_roots, o_ctr, o_act[MAXLEV + 1], o_leaves, o_big, o_sink, o_tileStart, o_blkStart,
       o_sampStart, o_samp, o_spl, o_tree, o_eq, o_hist, o_blkHist, o_tileOff,
       o_i2c, o_cfirst, o_cstart, o_cdst, o_nch, o_dbg, o_totals, o_strata;
   uint32_t capActMax, capTile, capBlk, capSBlk, maxHS, maxCH, maxM, maxS;

@@ -106,6 +106,7 @@ struct Ws {
   Strata *strata;  // per active subproblem of the next level: its parent buckets
   uint32_t capTile, capBlk, capSBlk;
   uint32_t *dbgHist, *dbgChildren, *dbgNChild;
+  uint64_t *sink;  // SINK_WORDS words that stores of empty slots go to (never read)
 };
 
 struct Lev {
@@ -1358,6 +1359,12 @@ __global__ void __launch_bounds__(256) k_scatter(Ws w, Lev lv) {
 // atomics instead of ballot ranks.  The next chunk's keys are loaded into
 // registers while the current one is classified, regrouped and written.
 constexpr uint32_t SCK_THREADS = 1024;
+// Stores of a chunk's empty slots (past the tile's end, or of a child that
+// would overrun its subproblem) go to a sink in the workspace instead of
+// being skipped: every store of the write-out is then unconditional, and the
+// compiler's count of outstanding memory operations stays exact, so the
+// next chunk's keys are waited for without waiting for the stores.
+constexpr uint32_t SINK_WORDS = SCK_THREADS * 8;
 
 // Chunk keys of a tile: the tile's keys are read through a buffer resource
 // over [tile start, tile end), 16 bytes per lane and load; chunk offset coff
@@ -1434,9 +1441,11 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
   const uint32_t CH = lv.CH;
   K *sTree = (K *)smem_raw;                       // mmax
   K *stK = sTree + lv.mmax;                       // CHK
-  uint64_t *sDst = (uint64_t *)(stK + CHK);       // CH: output address of chunk slot 0, per child
+  // CH + 2: output address of chunk slot 0, per child; entry CH: the sink
+  // (the second extra entry keeps the next arrays 16-byte aligned)
+  uint64_t *sDst = (uint64_t *)(stK + CHK);
   // PRIV: two banks of SCK_PCH counters and 16 rows of SCK_PCH offsets
-  uint32_t *sCnt2 = (uint32_t *)(sDst + CH);
+  uint32_t *sCnt2 = (uint32_t *)(sDst + CH + 2);
   uint16_t *sRows = (uint16_t *)(sCnt2 + (PRIV ? 2 * SCK_PCH : 0));
   uint16_t *stC = sRows + (PRIV ? (SCK_THREADS / 64) * SCK_PCH : 0);  // CHK
   uint16_t *sI2C = stC + CHK;                     // HS
@@ -1457,6 +1466,7 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
   } else {
     for (uint32_t c = tid; c < CH; c += SCK_THREADS) sCnt[c] = 0;
   }
+  if (tid == 0) sDst[CH] = (uint64_t)(uintptr_t)w.sink;  // slots past the chunk's end
   if (ir.first >= ir.end) return;
   // The keys of the first chunk of a tile are loaded while the previous
   // tile's last chunk is processed, so no tile starts on an empty pipeline.
@@ -1495,9 +1505,13 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
     // advanced only by thread c % SCK_THREADS, so no barrier is needed)
     for (uint32_t c = tid; c < nch; c += SCK_THREADS) sBase[c] = w.tileOff[(size_t)g * CH + c];
     for (uint32_t cb = lo; cb < hi; cb += CHK) {
+      // the next chunk: of this tile, else the first of the next tile, else
+      // an offset past the range (zeros); always issued, see SINK_WORDS
       K xb[KPT];
-      if (cb + CHK < hi) sck_load<KT, KPT>(rs, (cb + CHK - lo) * (uint32_t)sizeof(K), xb);
-      else if (more) sck_load<KT, KPT>(rsn, 0u, xb);
+      const bool inTile = cb + CHK < hi;
+      sck_load<KT, KPT>(inTile ? rs : rsn,
+                        inTile ? (cb + CHK - lo) * (uint32_t)sizeof(K) : (more ? 0u : 0x80000000u),
+                        xb);
       if (enc) {
 #pragma unroll
         for (int k = 0; k < KPT; ++k) xa[k] = Key<KT>::enc(xa[k]);
@@ -1539,18 +1553,19 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
         block_exscan_to<SCK_THREADS>(sCnt, sL, nch, sTmp);
       }
       // per child: the output address of chunk slot 0 (low bit: decode the
-      // key on the way out; 0: the child would overrun its subproblem and
-      // its keys are dropped, flagged as an overflow); then advance sBase
+      // key on the way out; a child that would overrun its subproblem has
+      // its keys sent to the sink, flagged as an overflow); then advance sBase
       for (uint32_t c = tid; c < nch; c += SCK_THREADS) {
         const uint32_t cd = sCd[c];
         const uint32_t nc = ccnt[c];
         const uint32_t lc = PRIV ? (uint32_t)off16[c] : sL[c];
-        uint64_t d = 0;
+        uint64_t d;
         if ((uint64_t)sBase[c] + nc <= s.size) {
           const K *base = kptr<K>(w, R, cd & 15u) + s.off + sBase[c];
           d = ((uint64_t)(uintptr_t)base - (uint64_t)lc * sizeof(K)) | (uint64_t)(cd >> 4);
         } else {
           raise_error(w.ctr, 16u);
+          d = (uint64_t)(uintptr_t)w.sink - (uint64_t)lc * sizeof(K);
         }
         sDst[c] = d;
         sBase[c] += nc;
@@ -1574,17 +1589,15 @@ __global__ void __launch_bounds__(SCK_THREADS, 1) k_scatter_keys(Ws w, Lev lv) {
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
         const uint32_t q = tid + SCK_THREADS * k;
-        cc[k] = q < cnt ? stC[q] : 0u;
-        xo[k] = q < cnt ? stK[q] : (K)0;
+        cc[k] = q < cnt ? stC[q] : CH;  // past the chunk's end: the sink
+        xo[k] = stK[q];
       }
 #pragma unroll
       for (int k = 0; k < KPT; ++k) {
         const uint32_t q = tid + SCK_THREADS * k;
-        const uint64_t d = q < cnt ? sDst[cc[k]] : 0ull;
-        if (d) {
-          const K x = (d & 1u) ? Key<KT>::dec(xo[k]) : xo[k];
-          *(GMem<K> *)((d & ~(uint64_t)1) + (uint64_t)q * sizeof(K)) = x;
-        }
+        const uint64_t d = sDst[cc[k]];
+        const K x = (d & 1u) ? Key<KT>::dec(xo[k]) : xo[k];
+        *(GMem<K> *)((d & ~(uint64_t)1) + (uint64_t)q * sizeof(K)) = x;
       }
       // no barrier here: every wavefront finishes this write-out before it
       // reaches the next chunk's first barrier, and the staging area is
@@ -3387,6 +3400,7 @@ ams_status make_plan(Plan &pl, int kt, bool pay, const uint64_t *sizes, uint32_t
     pl.o_strata = take(ns * sizeof(Strata));
   }
   pl.o_dbg = take((size_t)(nroots + 1) * 8);  // batch offsets upload / step outputs
+  pl.o_sink = take(SINK_WORDS * 8);
   pl.bytes = o;
   return AMS_OK;
 }
@@ -3424,6 +3438,7 @@ static Ws carve(const Plan &pl, char *base) {
   w.cdst = (uint8_t *)(base + pl.o_cdst);
   w.nch = (uint32_t *)(base + pl.o_nch);
   w.strata = (Strata *)(base + pl.o_strata);
+  w.sink = (uint64_t *)(base + pl.o_sink);
   w.capTile = pl.capTile;
   w.capBlk = pl.capBlk;
   w.capSBlk = pl.capSBlk;
@@ -3591,7 +3606,7 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
       // (large k * b) leave too little LDS for the larger staging area
       auto lds_keys = [&](uint32_t kpt) {
         const size_t chk = (size_t)SCK_THREADS * kpt;
-        return (size_t)ls.mmax * sizeof(K) + chk * sizeof(K) + (size_t)ls.CH * 8 + chk * 2 +
+        return (size_t)ls.mmax * sizeof(K) + chk * sizeof(K) + (size_t)(ls.CH + 2) * 8 + chk * 2 +
                (size_t)ls.HS * 2 + (size_t)ls.CH * 4 * 3 + SCK_THREADS / 64 * 4 + ls.CH + 64;
       };
       // with at most SCK_PCH children: per-wavefront scans and two counter
