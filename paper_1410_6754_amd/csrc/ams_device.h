@@ -206,15 +206,18 @@ AMS_DEV uint32_t wave_slot_add(uint32_t *ctr, uint32_t c, bool active) {
 // Add 1 to ctr[c] for every active lane (no slots returned), aggregated the
 // same way.
 AMS_DEV void wave_count_add(uint32_t *ctr, uint32_t c, bool active) {
-  const uint64_t act = ballot(active);
-  if (act == 0) return;
-  const uint32_t lead = (uint32_t)__builtin_ctzll(act);
-  const uint32_t c0 = __builtin_amdgcn_readlane(c, lead);
-  if (ballot(active && c == c0) == act) {
-    if (lane_id() == lead) atomicAdd(&ctr[c0], (uint32_t)__popcll(act));
-    return;
+  uint64_t act = ballot(active);
+  // up to four runs of equal values (a row of sorted keys crosses a bucket
+  // boundary now and then): one add per value, then one per lane
+  for (int round = 0; round < 4 && act; ++round) {
+    const uint32_t lead = (uint32_t)__builtin_ctzll(act);
+    const uint32_t c0 = __builtin_amdgcn_readlane(c, lead);
+    const uint64_t same = ballot(active && c == c0) & act;
+    if (lane_id() == lead) atomicAdd(&ctr[c0], (uint32_t)__popcll(same));
+    act &= ~same;
+    active = active && c != c0;
   }
-  if (active) atomicAdd(&ctr[c], 1u);
+  if (act && active) atomicAdd(&ctr[c], 1u);
 }
 
 template <typename T> AMS_DEV T wave_sum(T v) {
