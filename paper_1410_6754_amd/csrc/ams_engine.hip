@@ -1944,18 +1944,23 @@ AMS_DEV uint32_t cross_block_rank(const K *blk, uint32_t b, K x, uint32_t part, 
 //     and the positions they leave empty are filled with the same bits.
 //     Keys after a bucket are larger (buckets follow key order) and the pad
 //     holds the largest value, so a scan may run past its bucket unmasked.
-// In-LDS fan-out of a leaf of s keys: the smallest power of two f <= FMAX
+// In-LDS fan-out of a leaf of s keys: the smallest power of two f <= fmax
 // with s / f <= cutoff / 2 (1 when the leaf is not split).
-AMS_DEV uint32_t leaf_fanout(uint32_t s, uint32_t cutoff) {
+AMS_DEV uint32_t leaf_fanout(uint32_t s, uint32_t cutoff, uint32_t fmax) {
   uint32_t f = 1;
   if (s > cutoff) {
     const uint32_t tgt = cutoff / 2 > 4 ? cutoff / 2 : 4;
     const uint32_t need = (s + tgt - 1) / tgt;
     f = 2;
-    while (f < need && f < FMAX) f <<= 1;
+    while (f < need && f < fmax) f <<= 1;
   }
   return f;
 }
+// The range split of uint64 keys without payload may use up to FRMAX
+// buckets (one counter per thread): its keys sit in B as offsets from the
+// leaf's minimum shifted to the top of the word, whose top bits are the
+// bucket, so no bucket byte is stored per key.
+constexpr uint32_t FRMAX = FIN_THREADS;
 // log2 of the oversampling factor a of a leaf's sample (a = 4, 2, 1; the
 // sample a * f holds at most FMAX keys)
 AMS_DEV uint32_t leaf_loga(uint32_t logf) { return logf <= 6 ? 2u : 8u - logf; }
@@ -1973,7 +1978,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   GMem<K> *dst = (GMem<K> *)dst_;
   GMem<uint32_t> *vdst = (GMem<uint32_t> *)vdst_;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t f = leaf_fanout(s, cutoff);
+  const uint32_t f = leaf_fanout(s, cutoff, FMAX);
   const uint32_t logf = ilog2c(f);
   // placed-position bitmap: position p is bit p / nwb of word p % nwb, so
   // neighbouring positions fall in different words (C <= 32 * nwb)
@@ -2093,7 +2098,13 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
   bool zt = false;
   K zmn = 0;
   uint32_t zlsh = 0;
-  if (f > 1 && !sampled_only) {
+  // range split of offsets with up to FRMAX buckets: the bucket of the key
+  // at B[p] is B[p] >> zbs, and bid is not written
+  bool zbuck = false;
+  uint32_t zbs = 0;
+  const uint32_t fr = ZT ? leaf_fanout(s, cutoff, FRMAX) : f;  // range split's fan-out
+  const uint32_t logfr = ilog2c(fr);
+  if (fr > 1 && !sampled_only) {
     // ---- split by key range.  After the partition levels a leaf covers a
     // narrow range of keys, which most inputs fill about evenly; bucket b(x)
     // = (x - min) >> sh with sh chosen so that b < f.  b is monotone in x, so
@@ -2126,7 +2137,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
                                        ? __builtin_clzll((unsigned long long)range)
                                        : __builtin_clz((uint32_t)range))
                                 : 0u;
-    const uint32_t sh = bits > logf ? bits - logf : 0u;
+    const uint32_t sh = bits > logfr ? bits - logfr : 0u;
 #pragma unroll
     for (uint32_t k = 0; k < FIN_KPT; ++k)
       xir[k] = slot_valid(k) ? (uint32_t)((xk[k] - mn) >> sh) : 0u;
@@ -2135,11 +2146,13 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       zmn = mn;
       zlsh = (uint32_t)(8 * sizeof(K)) - bits;
     }
-    NB = f;
+    NB = fr;
     Lb = count_scan(NB);
-    const uint32_t avg = (s + f - 1) / f;
+    const uint32_t avg = (s + fr - 1) / fr;
     split = Lb <= (4 * avg > 64 ? 4 * avg : 64);
     if (!split && !PAY) sm.cnt[tid] = 0;  // counters for the sampled split
+    zbuck = ZT && zt && split;
+    zbs = zlsh + sh;  // z >> (64 - bits) is x - mn; >> sh more is the bucket
   }
   if (f > 1 && !split) {
     // ---- sampled split: S = a*f keys at random positions of the leaf
@@ -2231,7 +2244,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
       const uint32_t q = (PAY ? sm.cnt[wave * NB + id] : sm.bstart[id]) + (xir[k] & 0xFFFFu);
       sm.B[q] = (ZT && zt) ? (K)((xk[k] - zmn) << zlsh) : xk[k];
       if (PAY) sm.vB[q] = xv[k];
-      if (!eq) sm.bid[q] = (uint8_t)id;  // direct order: ids < f <= 256
+      if (!eq && !zbuck) sm.bid[q] = (uint8_t)id;  // direct order: ids < f <= 256
     }
   }
   if (s + Lb + 8 <= C + FIN_PAD)
@@ -2312,7 +2325,7 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     const uint32_t ps = tid + FIN_THREADS * k;
     r.valid = ps < s;
     const uint32_t pv = r.valid ? ps : 0u;
-    const uint32_t b = sm.bid[pv];
+    const uint32_t b = zbuck ? (uint32_t)((uint64_t)sm.B[pv] >> zbs) : (uint32_t)sm.bid[pv];
     r.isEq = eq && pv >= eqStart;  // equal keys: any arrangement is final
     const uint32_t id = eq ? 2 * b + (r.isEq ? 1u : 0u) : b;
     r.id = id;
