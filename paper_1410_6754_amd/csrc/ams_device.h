@@ -330,6 +330,22 @@ AMS_DEV ItemRange xcd_items(uint32_t total) {
   return r;
 }
 
+// One item per workgroup, for grids of 8 * ceil(total / 8) or more
+// workgroups: workgroup b takes item j = b / 8 of the contiguous eighth of
+// the items that XCD x = b mod 8 owns (an empty range past the items).  The
+// hardware hands the workgroups out as earlier ones finish, which balances
+// items of unequal sizes.
+AMS_DEV ItemRange xcd_item(uint32_t total) {
+  const uint32_t b = blockIdx.x, x = b & 7u, j = b >> 3;
+  const uint32_t chunk = (total + 7u) >> 3;
+  const uint32_t g = x * chunk + j;
+  ItemRange r;
+  r.first = g;
+  r.step = 1;
+  r.end = (j < chunk && g < total) ? g + 1 : g;
+  return r;
+}
+
 // Largest i in [0, n) with prefix[i] <= g (prefix non-decreasing, prefix[0] = 0).
 AMS_DEV uint32_t find_owner(const uint32_t *prefix, uint32_t n, uint32_t g) {
   uint32_t lo = 0, hi = n;  // answer in [lo, hi)

@@ -563,7 +563,10 @@ template <int KT> __global__ void __launch_bounds__(256) k_count(Ws w, Lev lv) {
   uint32_t *sH = (uint32_t *)(sTree + lv.mmax);  // NB
   const uint32_t tid = threadIdx.x;
   const uint32_t P = w.ctr->P;
-  ItemRange ir = xcd_items(w.ctr->ntile);
+  const uint32_t ntile = w.ctr->ntile;
+  ItemRange ir = xcd_item(ntile);  // one tile per workgroup
+  // the grid covers every tile (the plan bounds the count); else flagged
+  if (blockIdx.x == 0 && tid == 0 && 8u * ((ntile + 7u) / 8u) > gridDim.x) raise_error(w.ctr, 4u);
   uint32_t cur = 0xFFFFFFFFu;
   bool eq = false;
   uint32_t logm = 0, m = 0;
@@ -3559,7 +3562,8 @@ static ams_status run_typed(const Plan &pl, void *wsv, const RootSource &rs, hip
     allow_lds(k_count<KT>, ldsC);
     {
       TraceScope ts("count", l, s);
-      hipLaunchKernelGGL(k_count<KT>, dim3(grid_for(ls.tiles, 2048)), dim3(256), ldsC, s, w, lv);
+      // one workgroup per tile (ls.tiles bounds the level's tile count)
+      hipLaunchKernelGGL(k_count<KT>, dim3(8 * ((ls.tiles + 7) / 8)), dim3(256), ldsC, s, w, lv);
     }
     {
       TraceScope ts("block_reduce", l, s);
