@@ -37,7 +37,7 @@ namespace {
 constexpr uint32_t RLM_NT = 256;        // selection threads (one sequence each)
 constexpr uint32_t RLM_M = 8;           // pivots per selection step
 constexpr uint32_t RLM_NONE = 0xFFu;    // "keep this end of the windows"
-constexpr uint32_t RLM_WAVE_SEQ = 256;  // groups of at most this many sequences: one wave per selection
+constexpr uint32_t RLM_GROUP_SEQ = RLM_NT;  // groups of at most this many sequences: whole selections per workgroup
 constexpr uint32_t RLM_MT = 512;        // merge threads
 constexpr uint32_t RLM_TMAX = 4096;     // largest tile (LDS of the merge)
 constexpr uint32_t RLM_MAXLEV = 16;
@@ -67,7 +67,6 @@ struct RSel {
   uint32_t total;                // keys in the windows
   uint32_t mlo, mhi;             // decision to apply: windows [cc[mlo], cc[mhi]) (RLM_NONE: keep)
   uint32_t done;                 // 1: the windows' upper ends (after the decision) are the cut
-  uint32_t arrive;               // blocks of the current step that have finished
   uint32_t iter;
 };
 
@@ -333,7 +332,6 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_sel_init(RWs w, RLev lv, const v
         sp->mlo = RLM_NONE;
         sp->mhi = RLM_NONE;
         sp->done = C.j == 0 ? 1u : 0u;  // the first part starts at rank 0
-        sp->arrive = 0;
         sp->iter = 0;
       }
     }
@@ -364,140 +362,204 @@ AMS_DEV void sel_entry(const RWs &w, const RGroup &P, uint32_t e, uint32_t i, ui
   W = hi - lo;
 }
 
-// Small groups (at most RLM_WAVE_SEQ sequences): one wavefront runs a whole
-// selection, steps back to back (at most lv.itmax), up to four sequences
-// per lane.
+// Segments of G lanes (G a power of two) inside a workgroup of RLM_NT
+// threads: sums and inclusive scans over a segment.  G <= 64 stays inside a
+// wavefront; G = 128 or 256 spans waves and meets in LDS (every thread of
+// the workgroup must call these: they hold barriers then).
+AMS_DEV void seg_sum8(uint32_t (&v)[RLM_M], uint32_t G, uint32_t *red) {
+  constexpr uint32_t NW = RLM_NT / 64;
+  if (G <= 64) {
+    for (uint32_t d = 1; d < G; d <<= 1) {
+#pragma unroll
+      for (uint32_t m = 0; m < RLM_M; ++m) v[m] += __shfl_xor(v[m], d, 64);
+    }
+    return;
+  }
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (uint32_t m = 0; m < RLM_M; ++m) v[m] = wave_sum(v[m]);
+  if (lane == 0) {
+#pragma unroll
+    for (uint32_t m = 0; m < RLM_M; ++m) red[m * NW + wave] = v[m];
+  }
+  __syncthreads();
+  const uint32_t gw = G >> 6, w0 = wave & ~(gw - 1u);
+#pragma unroll
+  for (uint32_t m = 0; m < RLM_M; ++m) {
+    uint32_t s = 0;
+    for (uint32_t q = 0; q < gw; ++q) s += red[m * NW + w0 + q];
+    v[m] = s;
+  }
+}
+
+AMS_DEV uint32_t seg_incl_scan(uint32_t v, uint32_t G, uint32_t *carry) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  if (G <= 64) {
+    const uint32_t k = lane & (G - 1u);
+    for (uint32_t d = 1; d < G; d <<= 1) {
+      const uint32_t y = __shfl_up(v, d, 64);
+      if (k >= d) v += y;
+    }
+    return v;
+  }
+  v = wave_incl_scan(v);
+  if (lane == 63) carry[wave] = v;
+  __syncthreads();
+  const uint32_t w0 = wave & ~((G >> 6) - 1u);
+  for (uint32_t q = w0; q < wave; ++q) v += carry[q];
+  return v;
+}
+
+// Groups of at most RLM_GROUP_SEQ sequences: a workgroup runs whole
+// selections, every step, one sequence per thread, the windows in
+// registers.  A segment of G threads (G a power of two, at least the
+// group's sequence count) holds one selection, so a workgroup holds
+// RLM_NT / G selections; a step counts, sums the counts over the segment,
+// decides (every thread of the segment alike), and draws the next pivots
+// from the windows that remain (Section 4.1).
 template <int KT>
-__global__ void __launch_bounds__(RLM_NT) k_rlm_select_wave(RWs w, RLev lv, const void *src_) {
+__global__ void __launch_bounds__(RLM_NT) k_rlm_select_group(RWs w, RLev lv, const void *src_,
+                                                             uint32_t G) {
   typedef typename Key<KT>::T K;
+  constexpr uint32_t NW = RLM_NT / 64, SMAX = RLM_NT / 4;  // G >= 4
   const GMem<K> *src = (const GMem<K> *)src_;
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t nc = w.hdr->nChildren;
-  const uint32_t waves = gridDim.x * (RLM_NT / 64);
-  for (uint32_t c = blockIdx.x * (RLM_NT / 64) + (threadIdx.x >> 6); c < nc; c += waves) {
-    const RGroup C = w.children[c];
-    const RGroup P = w.groups[C.parent];
-    const uint32_t S = (P.size + lv.T - 1) / lv.T;
-    if (S > RLM_WAVE_SEQ) continue;  // the block kernel's
-    RSel *sp = w.sel + c;
-    uint32_t np = sp->np, krem = sp->krem, total = sp->total, mlo = sp->mlo, mhi = sp->mhi;
-    uint32_t done = sp->done, iter = sp->iter;
+  __shared__ uint32_t red[RLM_M * NW];
+  __shared__ uint32_t carry[NW];
+  __shared__ uint64_t spv[2][SMAX * RLM_M];  // the next pivots, by step parity
+  __shared__ uint32_t spq[2][SMAX * RLM_M], spt[2][SMAX * RLM_M];
+  const uint32_t tid = threadIdx.x, nc = w.hdr->nChildren;
+  const uint32_t per = RLM_NT / G, sl = tid / G, i = tid & (G - 1u);
+  for (uint32_t c0 = blockIdx.x * per; c0 < nc; c0 += gridDim.x * per) {
+    const uint32_t c = c0 + sl;
+    bool valid = c < nc;
+    RGroup C, P;
+    uint32_t S = 0;
+    if (valid) {
+      C = w.children[c];
+      P = w.groups[C.parent];
+      S = (P.size + lv.T - 1) / lv.T;
+      valid = S <= G;  // wider groups: the block kernels'
+    }
+    RSel *sp = w.sel + (valid ? c : 0u);
+    uint32_t np = 0, krem = 0, total = 0, done = 1, iter = 0;
     uint64_t pv[RLM_M];
     uint32_t pq[RLM_M], pt[RLM_M];
 #pragma unroll
     for (uint32_t m = 0; m < RLM_M; ++m) {
-      pv[m] = sp->pv[m];
-      pq[m] = sp->pq[m];
-      pt[m] = sp->pt[m];
+      pv[m] = 0;
+      pq[m] = pt[m] = 0;
     }
-    for (uint32_t step = 0; step < lv.itmax && !done; ++step) {
-      uint32_t Lsum[RLM_M];
+    if (valid) {
+      np = sp->np;
+      krem = sp->krem;
+      total = sp->total;
+      done = sp->done;
+      iter = sp->iter;
 #pragma unroll
-      for (uint32_t m = 0; m < RLM_M; ++m) Lsum[m] = 0;
-      for (uint32_t k = 0; k < RLM_WAVE_SEQ / 64; ++k) {
-        const uint32_t i = k * 64 + lane;
-        if (i < S) {
-          uint32_t L[RLM_M], Wi;
-          sel_entry<KT>(w, P, C.cutBase + i, i, lv.T, mlo, mhi, np, pv, pq, pt, src, L, Wi);
+      for (uint32_t m = 0; m < RLM_M; ++m) {
+        pv[m] = sp->pv[m];
+        pq[m] = sp->pq[m];
+        pt[m] = sp->pt[m];
+      }
+    }
+    const bool mine = valid && i < S;  // this thread's sequence exists
+    const uint32_t e = mine ? C.cutBase + i : 0u;
+    uint32_t lo = 0, hi = 0;
+    if (mine) {
+      lo = w.lo[e];
+      hi = w.hi[e];
+    }
+    const GMem<K> *x = src + (mine ? P.start + (size_t)i * lv.T : 0);
+    uint32_t err = 0;
+    for (uint32_t step = 0; step < lv.itmax; ++step) {
+      if (!__syncthreads_or(done ? 0 : 1)) break;  // every selection here is done
+      const uint32_t par = step & 1u;
+      uint32_t cnt[RLM_M];
+      if (mine && !done) {
+        count_before_all<KT>(x, lo, hi, pv, pq, pt, np, i, cnt);
+      } else {
 #pragma unroll
-          for (uint32_t m = 0; m < RLM_M; ++m) Lsum[m] += L[m];
-        }
+        for (uint32_t m = 0; m < RLM_M; ++m) cnt[m] = lo;
       }
       uint32_t left[RLM_M];
 #pragma unroll
-      for (uint32_t m = 0; m < RLM_M; ++m) left[m] = wave_sum(Lsum[m]);
-      const RDecision d = decide(left, np, krem, total);
-      mlo = d.mlo;
-      mhi = d.mhi;
-      krem = d.krem;
-      total = d.total;
-      done = d.done;
-      ++iter;
-      if (done) break;
-      // next pivots: draw m is the u-th key of the new windows in sequence
-      // order; each lane holds four sequences' window sizes
-      uint32_t wlo[RLM_WAVE_SEQ / 64], wsz[RLM_WAVE_SEQ / 64], lsum = 0;
-      for (uint32_t k = 0; k < RLM_WAVE_SEQ / 64; ++k) {
-        const uint32_t i = lane * (RLM_WAVE_SEQ / 64) + k;  // lane-major for the scan
-        uint32_t a = 0, b = 0;
-        if (i < S) {
-          const uint32_t e = C.cutBase + i;
-          a = mlo == RLM_NONE ? w.lo[e] : w.cc[(size_t)mlo * w.capCut + e];
-          b = mhi == RLM_NONE ? w.hi[e] : w.cc[(size_t)mhi * w.capCut + e];
-        }
-        wlo[k] = a;
-        wsz[k] = b - a;
-        lsum += b - a;
-      }
-      const uint32_t incl = wave_incl_scan(lsum);
-      np = total < RLM_M ? total : RLM_M;
-      // the draws: the lane whose sequences hold key u of the windows finds
-      // the sequence and position and loads the pivot; all draws at once
-      uint32_t myq[RLM_M], myt[RLM_M];
-      uint64_t myv[RLM_M];
-      bool own[RLM_M];
+      for (uint32_t m = 0; m < RLM_M; ++m) left[m] = cnt[m] - lo;
+      seg_sum8(left, G, red);
+      uint32_t z = 0;
+      if (!done) {
+        const RDecision d = decide(left, np, krem, total);
+        uint32_t nlo = lo, nhi = hi;
 #pragma unroll
-      for (uint32_t m = 0; m < RLM_M; ++m) {
-        const uint32_t u = m < np ? pivot_draw(lv, c, iter, m, total) : 0xFFFFFFFFu;
-        own[m] = u >= incl - lsum && u < incl;
-        uint32_t r = u - (incl - lsum), q = 0, t = 0;
-        bool found = false;
-#pragma unroll
-        for (uint32_t k = 0; k < RLM_WAVE_SEQ / 64; ++k) {
-          const bool here = own[m] && !found && r < wsz[k];
-          q = here ? lane * (RLM_WAVE_SEQ / 64) + k : q;
-          t = here ? wlo[k] + r : t;
-          r -= (own[m] && !found && !here) ? wsz[k] : 0u;
-          found = found || here;
+        for (uint32_t m = 0; m < RLM_M; ++m) {
+          nlo = m == d.mlo ? cnt[m] : nlo;
+          nhi = m == d.mhi ? cnt[m] : nhi;
         }
-        own[m] = own[m] && found;
-        myq[m] = q;
-        myt[m] = t;
-        myv[m] = own[m] ? (uint64_t)Key<KT>::enc(src[P.start + (size_t)q * lv.T + t]) : 0ull;
+        lo = nlo;
+        hi = nhi;
+        krem = d.krem;
+        total = d.total;
+        done = d.done;
+        ++iter;
+        z = done ? 0u : hi - lo;
       }
-      uint32_t got = np;
-#pragma unroll
-      for (uint32_t m = 0; m < RLM_M; ++m) {
-        if (m >= np) break;
-        const uint64_t owner = ballot(own[m]);
-        if (!owner) {  // cannot happen: the window sizes cover u
-          got = m < got ? m : got;
-          continue;
+      const uint32_t incl = seg_incl_scan(z, G, carry);
+      if (!done) {
+        // the draws: key u of the windows in sequence order lies in the
+        // window of the thread whose scan range holds it
+        np = total < RLM_M ? total : RLM_M;
+        const uint32_t excl = incl - z;
+        for (uint32_t m = 0; m < np; ++m) {
+          const uint32_t u = pivot_draw(lv, c, iter, m, total);
+          if (u >= excl && u < incl) {
+            const uint32_t t = lo + (u - excl);
+            spv[par][sl * RLM_M + m] = (uint64_t)Key<KT>::enc(x[t]);
+            spq[par][sl * RLM_M + m] = i;
+            spt[par][sl * RLM_M + m] = t;
+          }
         }
-        const uint32_t sl = (uint32_t)__builtin_ctzll(owner);
-        pq[m] = __shfl(myq[m], sl, 64);
-        pt[m] = __shfl(myt[m], sl, 64);
-        pv[m] = __shfl(myv[m], sl, 64);
+        if (i == G - 1u && incl != total) err = 1;  // the windows must hold `total` keys
       }
-      if (got < np) {
-        if (lane == 0) rlm_error(w, AMS_DEVERR_RANGE);
-        np = got;
+      __syncthreads();
+      if (!done) {
+#pragma unroll
+        for (uint32_t m = 0; m < RLM_M; ++m) {
+          if (m < np) {
+            pv[m] = spv[par][sl * RLM_M + m];
+            pq[m] = spq[par][sl * RLM_M + m];
+            pt[m] = spt[par][sl * RLM_M + m];
+          }
+        }
       }
     }
-    if (lane == 0) {
+    if (err) rlm_error(w, AMS_DEVERR_RANGE);
+    if (mine) {
+      w.lo[e] = lo;
+      w.hi[e] = hi;
+    }
+    if (valid && i == 0) {
       sp->np = np;
       sp->krem = krem;
       sp->total = total;
-      sp->mlo = mlo;
-      sp->mhi = mhi;
+      sp->mlo = RLM_NONE;  // the windows above are final
+      sp->mhi = RLM_NONE;
       sp->done = done;
       sp->iter = iter;
     }
   }
 }
 
-// Large groups: one step of every unfinished selection per launch; an item
-// is (selection, block of RLM_NT sequences).  The last block of a selection
-// to finish the step decides and draws the next pivots.
+// Wider groups, one step of every unfinished selection per pair of
+// launches.  Count: an item is (selection, block of RLM_NT sequences); each
+// applies the previous decision to its windows, counts the keys before each
+// pivot and leaves the block's sums.  The kernel boundary orders those sums
+// before the decide kernel reads them.
 template <int KT>
-__global__ void __launch_bounds__(RLM_NT) k_rlm_select_blocks(RWs w, RLev lv, const void *src_) {
+__global__ void __launch_bounds__(RLM_NT) k_rlm_sel_count(RWs w, RLev lv, const void *src_) {
   typedef typename Key<KT>::T K;
   const GMem<K> *src = (const GMem<K> *)src_;
   constexpr uint32_t NW = RLM_NT / 64;
   constexpr uint32_t PB = RLM_M + 1;  // partials per block
   __shared__ uint32_t red[PB * NW];
-  __shared__ uint32_t sh[8];
-  __shared__ uint32_t sleft[RLM_M];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t nb = w.hdr->cnt[1];
   for (uint32_t item = blockIdx.x; item < nb; item += gridDim.x) {
@@ -505,10 +567,9 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_select_blocks(RWs w, RLev lv, co
     const RGroup C = w.children[c];
     const RGroup P = w.groups[C.parent];
     const uint32_t S = (P.size + lv.T - 1) / lv.T;
-    if (S <= RLM_WAVE_SEQ) continue;  // the wave kernel's
-    RSel *sp = w.sel + c;
-    if (vload(&sp->done)) continue;
-    const uint32_t nblk = (S + RLM_NT - 1) / RLM_NT;
+    if (S <= RLM_GROUP_SEQ) continue;  // the group kernel's
+    const RSel *sp = w.sel + c;
+    if (sp->done) continue;
     const uint32_t b = item - C.blkBase;
     const uint32_t np = sp->np, mlo = sp->mlo, mhi = sp->mhi;
     uint64_t pv[RLM_M];
@@ -538,15 +599,32 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_select_blocks(RWs w, RLev lv, co
       for (uint32_t q = 0; q < NW; ++q) v += red[tid * NW + q];
       w.bl[(size_t)(C.blkBase + b) * PB + tid] = v;
     }
-    __threadfence();
     __syncthreads();
-    if (tid == 0) sh[0] = atomicAdd(&sp->arrive, 1u) + 1 == nblk ? 1u : 0u;
-    __syncthreads();
-    if (!sh[0]) continue;  // another block finishes this step
-    __threadfence();
-    // --- last block of the step: sum the partials and decide -------------
-    // (plain loads: the fence after the arrival count orders them after the
-    // other blocks' writes)
+  }
+}
+
+// Decide: one workgroup per unfinished selection sums the block sums,
+// decides which windows remain and draws the next pivots from them.
+template <int KT>
+__global__ void __launch_bounds__(RLM_NT) k_rlm_sel_decide(RWs w, RLev lv, const void *src_) {
+  typedef typename Key<KT>::T K;
+  const GMem<K> *src = (const GMem<K> *)src_;
+  constexpr uint32_t NW = RLM_NT / 64;
+  constexpr uint32_t PB = RLM_M + 1;
+  __shared__ uint32_t red[PB * NW];
+  __shared__ uint32_t sleft[RLM_M];
+  __shared__ uint32_t sbq[RLM_M], srr[RLM_M];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint32_t nc = w.hdr->nChildren;
+  for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+    const RGroup C = w.children[c];
+    const RGroup P = w.groups[C.parent];
+    const uint32_t S = (P.size + lv.T - 1) / lv.T;
+    if (S <= RLM_GROUP_SEQ) continue;
+    RSel *sp = w.sel + c;
+    if (sp->done) continue;
+    const uint32_t nblk = (S + RLM_NT - 1) / RLM_NT;
+    const uint32_t np = sp->np;
     const uint32_t *blp = w.bl + (size_t)C.blkBase * PB;
     {
       uint32_t acc[RLM_M];
@@ -558,7 +636,6 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_select_blocks(RWs w, RLev lv, co
       }
 #pragma unroll
       for (uint32_t m = 0; m < RLM_M; ++m) acc[m] = wave_sum(acc[m]);
-      __syncthreads();
       if (lane == 0) {
 #pragma unroll
         for (uint32_t m = 0; m < RLM_M; ++m) red[m * NW + wave] = acc[m];
@@ -590,14 +667,13 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_select_blocks(RWs w, RLev lv, co
       uint32_t mine = 0;
       for (uint32_t q = q0; q < q1; ++q) mine += bsize(q);
       const uint32_t incl = wave_incl_scan(mine);
+      __syncthreads();
       if (lane == 63) red[wave] = incl;
+      if (tid < RLM_M) sbq[tid] = 0xFFFFFFFFu;
       __syncthreads();
       uint32_t off = 0;
       for (uint32_t q = 0; q < wave; ++q) off += red[q];
       const uint32_t first = off + incl - mine;
-      __shared__ uint32_t sbq[RLM_M], srr[RLM_M];
-      if (tid < RLM_M) sbq[tid] = 0xFFFFFFFFu;
-      __syncthreads();
       for (uint32_t m = 0; m < np2; ++m) {
         const uint32_t u = pivot_draw(lv, c, iter, m, d.total);
         if (mine && u >= first && u < first + mine) {
@@ -652,8 +728,12 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_select_blocks(RWs w, RLev lv, co
           sp->pv[m] = (uint64_t)Key<KT>::enc(src[P.start + (size_t)ii * lv.T + t]);
         }
       }
-      __syncthreads();
+      if (tid == 0) {
+        for (uint32_t m = 0; m < np2; ++m)
+          if (sbq[m] >= nblk) rlm_error(w, AMS_DEVERR_RANGE);  // a draw outside the windows
+      }
     }
+    __syncthreads();
     if (tid == 0) {
       sp->np = np2;
       sp->krem = d.krem;
@@ -662,8 +742,6 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_select_blocks(RWs w, RLev lv, co
       sp->mhi = d.mhi;
       sp->done = d.done;
       sp->iter = iter;
-      sp->arrive = 0;
-      __threadfence();
     }
     __syncthreads();
   }
@@ -931,7 +1009,7 @@ struct RPlan {
   // per level: groups entering it, and the largest tables it fills
   uint32_t maxGroups, maxChildren, maxCut, maxBlk, maxQ, maxSlice;
   uint32_t itmax[RLM_MAXLEV];
-  bool multiblock[RLM_MAXLEV];
+  uint64_t maxS[RLM_MAXLEV];  // largest group of each level, in sequences
   size_t o_hdr, o_tmp, o_tile, o_g0, o_g1, o_sel, o_lo, o_hi, o_cc, o_cut, o_bl, o_bown, o_sown,
       o_si0, o_si1, o_q, o_scr, bytes;
 };
@@ -1001,7 +1079,7 @@ ams_status make_rlm_plan(RPlan &pl, ams_key_t t, uint64_t n, const ams_rlm_param
     }
     uint64_t maxS = 0;
     for (uint64_t N : sizes) maxS = std::max(maxS, (N + pl.T - 1) / pl.T);
-    pl.multiblock[L] = maxS > RLM_WAVE_SEQ;
+    pl.maxS[L] = maxS;
     pl.itmax[L] = sel_steps(mx);
     pl.maxChildren = std::max<uint32_t>(pl.maxChildren, (uint32_t)next.size());
     pl.maxCut = std::max<uint32_t>(pl.maxCut, (uint32_t)cut);
@@ -1045,20 +1123,33 @@ uint32_t grid_cap(uint64_t items, uint32_t cap) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(items, cap));
 }
 
-// All selections of a level: the wave kernel runs the small groups' whole
-// selections in one launch, the block kernel one step of the large groups'
-// per launch.
+// Segment width of the group kernel: a power of two, at least 4 (so a
+// workgroup holds at most RLM_NT / 4 selections), at least the level's
+// largest group up to RLM_GROUP_SEQ sequences.
+uint32_t group_width(uint64_t maxS) {
+  uint32_t G = 4;
+  while (G < maxS && G < RLM_GROUP_SEQ) G <<= 1;
+  return G;
+}
+
+// All selections of a level: the group kernel runs the small groups' whole
+// selections in one launch; the wider groups take one step per pair of
+// count and decide launches.
 template <int KT>
 void select_level(const RWs &w, const RLev &lv, const void *src, uint32_t maxChildren,
-                  uint32_t maxBlk, bool multiblock, hipStream_t s) {
+                  uint32_t maxBlk, uint64_t maxS, hipStream_t s) {
   hipLaunchKernelGGL(k_rlm_sel_init<KT>, dim3(grid_cap(maxChildren, 2048)), dim3(RLM_NT), 0, s, w,
                      lv, src);
-  hipLaunchKernelGGL(k_rlm_select_wave<KT>, dim3(grid_cap((maxChildren + 3) / 4, 4096)),
-                     dim3(RLM_NT), 0, s, w, lv, src);
-  if (multiblock)
-    for (uint32_t it = 0; it < lv.itmax; ++it)
-      hipLaunchKernelGGL(k_rlm_select_blocks<KT>, dim3(grid_cap(maxBlk, 4096)), dim3(RLM_NT), 0, s,
-                         w, lv, src);
+  const uint32_t G = group_width(maxS), per = RLM_NT / G;
+  hipLaunchKernelGGL(k_rlm_select_group<KT>, dim3(grid_cap((maxChildren + per - 1) / per, 4096)),
+                     dim3(RLM_NT), 0, s, w, lv, src, G);
+  if (maxS > RLM_GROUP_SEQ)
+    for (uint32_t it = 0; it < lv.itmax; ++it) {
+      hipLaunchKernelGGL(k_rlm_sel_count<KT>, dim3(grid_cap(maxBlk, 4096)), dim3(RLM_NT), 0, s, w,
+                         lv, src);
+      hipLaunchKernelGGL(k_rlm_sel_decide<KT>, dim3(grid_cap(maxChildren, 2048)), dim3(RLM_NT), 0,
+                         s, w, lv, src);
+    }
   hipLaunchKernelGGL(k_rlm_cut, dim3(grid_cap(maxChildren, 2048)), dim3(RLM_NT), 0, s, w, lv);
 }
 
@@ -1117,7 +1208,7 @@ ams_status rlm_typed(const RPlan &pl, const void *in, void *out, void *wsv, hipS
     }
     {
       TraceScope ts("rlm_select", l, s);
-      select_level<KT>(w, lv, src, pl.maxChildren, pl.maxBlk, pl.multiblock[l], s);
+      select_level<KT>(w, lv, src, pl.maxChildren, pl.maxBlk, pl.maxS[l], s);
     }
     {
       TraceScope ts("rlm_pieces", l, s);
@@ -1215,7 +1306,7 @@ ams_status step_select_typed(const void *d_runs, uint64_t n, uint32_t T, uint32_
   hipLaunchKernelGGL(k_rlm_root, dim3(1), dim3(64), 0, s, w, (uint32_t)n);
   hipLaunchKernelGGL(k_rlm_children, dim3(1), dim3(1024), 0, s, w, lv);
   hipLaunchKernelGGL(k_rlm_owners, dim3(grid_cap(parts, 2048)), dim3(RLM_NT), 0, s, w, lv);
-  select_level<KT>(w, lv, d_runs, parts, (uint32_t)blk, S > RLM_WAVE_SEQ, s);
+  select_level<KT>(w, lv, d_runs, parts, (uint32_t)blk, S, s);
   hipLaunchKernelGGL(k_rlm_last_row, dim3(grid_cap((S + 255) / 256, 1024)), dim3(256), 0, s,
                      d_cuts, parts, (uint32_t)S, n, T);
   uint32_t bits = 0;
