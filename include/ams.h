@@ -399,7 +399,9 @@ ams_status ams_step_level(ams_key_t t, const void *d_in, void *d_out, size_t n,
  * of d_cuts (parts+1 rows of ceil(n / run_keys) uint32 entries, device)
  * receives, for every run, how many of its keys are among the
  * floor(j n / parts) smallest.  1 <= parts <= min(1024, n).  Synchronises
- * `stream`; AMS_EDEVICE if a selection did not finish. */
+ * `stream`; AMS_EDEVICE if a selection did not finish.  Runs that are not
+ * sorted give unspecified cuts (AMS_EDEVICE where the selection notices)
+ * but every read stays inside its run. */
 ams_status ams_step_multiselect(ams_key_t t, const void *d_runs, size_t n, uint32_t run_keys,
                                 uint32_t parts, uint64_t seed, uint32_t *d_cuts, void *stream);
 

@@ -349,6 +349,10 @@ AMS_DEV void sel_entry(const RWs &w, const RGroup &P, uint32_t e, uint32_t i, ui
   uint32_t lo = w.lo[e], hi = w.hi[e];
   if (mlo != RLM_NONE) lo = w.cc[(size_t)mlo * w.capCut + e];
   if (mhi != RLM_NONE) hi = w.cc[(size_t)mhi * w.capCut + e];
+  if (hi < lo) {  // only a sequence that is not sorted inverts a window
+    rlm_error(w, AMS_DEVERR_RANGE);
+    hi = lo;
+  }
   w.lo[e] = lo;
   w.hi[e] = hi;
   const GMem<K> *x = src + P.start + (size_t)i * T;
@@ -493,6 +497,10 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_select_group(RWs w, RLev lv, con
         for (uint32_t m = 0; m < RLM_M; ++m) {
           nlo = m == d.mlo ? cnt[m] : nlo;
           nhi = m == d.mhi ? cnt[m] : nhi;
+        }
+        if (nhi < nlo) {  // only a sequence that is not sorted inverts a window
+          err = 1;
+          nhi = nlo;
         }
         lo = nlo;
         hi = nhi;
@@ -701,7 +709,7 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_sel_decide(RWs w, RLev lv, const
           const uint32_t lo_ = d.mlo == RLM_NONE ? w.lo[e] : w.cc[(size_t)d.mlo * w.capCut + e];
           const uint32_t hi_ = d.mhi == RLM_NONE ? w.hi[e] : w.cc[(size_t)d.mhi * w.capCut + e];
           za[m] = lo_;
-          zs[m] = hi_ - lo_;
+          zs[m] = hi_ > lo_ ? hi_ - lo_ : 0u;  // inverted only over unsorted sequences
         }
       }
       uint32_t inc2[RLM_M];

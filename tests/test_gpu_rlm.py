@@ -90,3 +90,25 @@ def test_rlm_two_levels_large(api):
     n = (1 << 22) + 12345
     log("rlm two+ levels n=%d" % n)
     check_rlm(api, U64, gen(U64, n, "uniform", 750), what="rlm 2^22+")
+
+
+@pytest.mark.parametrize("n,run_keys,parts", [(20000, 100, 9), (200000, 500, 16)])
+def test_step_multiselect_unsorted_runs_stay_in_bounds(api, n, run_keys, parts):
+    """Runs that are not sorted break the selection's premise: the cuts are
+    unspecified, but every window stays inside its run (a window that would
+    invert is emptied and the call may report a device error), and a sorted
+    call afterwards is exact.  Covers the workgroup path (200 runs) and the
+    count/decide path (400 runs)."""
+    from paper_1410_6754_amd import _lib as L
+    keys = gen(U64, n, "uniform", 760 + parts)  # not sorted within the runs
+    log("multiselect over unsorted runs n=%d runs of %d, %d parts" % (n, run_keys, parts))
+    try:
+        api.step_multiselect(to_dev(keys), run_keys, parts)
+    except L.AmsError as e:
+        assert e.status == L.AMS_EDEVICE
+    runs = runs_sorted(U64, keys, run_keys)
+    got = to_host(api.step_multiselect(to_dev(runs), run_keys, parts))
+    ords = oracle.ord_keys(U64, runs)
+    seqs = [[int(v) for v in ords[a:a + run_keys]] for a in range(0, n, run_keys)]
+    want = np.array(orlm.rlm_splits(seqs, parts), dtype=np.uint32)
+    assert np.array_equal(got, want)
