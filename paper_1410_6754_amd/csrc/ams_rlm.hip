@@ -831,6 +831,12 @@ AMS_DEV uint32_t upper_le(const uint32_t *v, uint32_t n, uint32_t x) {
   return lo;
 }
 
+// Key slots of the merge buffers: one spare slot after every 16 keys, so
+// threads that work on runs of keys 4 to 8 apart (as the merge rounds'
+// threads do) meet in different LDS banks.
+AMS_DEV uint32_t lpad(uint32_t x) { return x + (x >> 4); }
+AMS_HD uint32_t lpad_size(uint32_t T) { return T + (T >> 4); }
+
 template <int KT>
 __global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const void *src_,
                                                          void *dst_) {
@@ -841,10 +847,10 @@ __global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const v
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const uint32_t T = lv.T;
   K *bufA = (K *)smem_raw;
-  K *bufB = bufA + T;
+  K *bufB = bufA + lpad_size(T);
   // segment starts relative to the slice (< T, so 16 bits): first the
   // pieces' offsets, then the merge's segments
-  uint16_t *seg = (uint16_t *)(bufB + T);  // T + 1 entries
+  uint16_t *seg = (uint16_t *)(bufB + lpad_size(T));  // T + 1 entries
   __shared__ uint32_t tmp[RLM_MT / 64];
   __shared__ uint32_t shd[2];
   const uint32_t tid = threadIdx.x;
@@ -878,7 +884,7 @@ __global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const v
     const uint32_t lead = shd[0];
     // gather: key x of the slice comes from the piece holding a + x; the
     // piece searches first, then all loads in flight together
-    uint32_t *flag = (uint32_t *)bufB;
+    uint32_t *flag = (uint32_t *)bufB;  // piece starts, when too many pieces for seg
     uint32_t pi[PT], pp[PT];
     bool ok[PT];
 #pragma unroll
@@ -908,7 +914,7 @@ __global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const v
       pp[u] = pos;
       ok[u] = ok[u] && pos < seq_len(P, i, T);
       if (x < len && !ok[u]) rlm_error(w, AMS_DEVERR_RANGE);  // cannot happen
-      if (x < len) flag[x] = (x == 0 || (k != 0 && rel == x)) ? 1u : 0u;  // a piece starts here
+      if (!cached && x < len) flag[x] = (x == 0 || (k != 0 && rel == x)) ? 1u : 0u;
     }
     K v[PT];
 #pragma unroll
@@ -917,19 +923,44 @@ __global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const v
 #pragma unroll
     for (uint32_t u = 0; u < PT; ++u) {
       const uint32_t x = tid + u * RLM_MT;
-      if (x < len) bufA[x] = v[u];
+      if (x < len) bufA[lpad(x)] = v[u];
     }
     __syncthreads();
-    const uint32_t nseg = block_exscan<RLM_MT>(flag, len, tmp);
-    // flag[] now holds ranks; a start is where the rank steps
-    for (uint32_t x = tid; x < len; x += RLM_MT) {
-      const uint32_t rk = flag[x];
-      const uint32_t nx = x + 1 < len ? flag[x + 1] : nseg;
-      if (nx != rk) seg[rk] = (uint16_t)x;
+    uint32_t nseg;
+    if (cached) {
+      // the merge's segments are the non-empty pieces: their starts,
+      // compacted in place by the first wave (an entry moves down only)
+      if (tid < 64) {
+        uint32_t base = 0;
+        for (uint32_t k0 = 0; k0 < np; k0 += 64) {
+          const uint32_t k = k0 + tid;
+          const uint32_t s0 = k < np ? seg[k] : 0u, s1 = k < np ? seg[k + 1] : 0u;
+          const bool keep = k < np && s1 > s0;
+          const uint64_t mk = ballot(keep);
+          if (keep) seg[base + bits_below(mk)] = (uint16_t)s0;
+          base += (uint32_t)__builtin_popcountll(mk);
+        }
+        if (tid == 0) {
+          seg[base] = (uint16_t)len;
+          shd[1] = base;
+        }
+      }
+      __syncthreads();
+      nseg = shd[1];
+    } else {
+      nseg = block_exscan<RLM_MT>(flag, len, tmp);
+      // flag[] now holds ranks; a start is where the rank steps
+      for (uint32_t x = tid; x < len; x += RLM_MT) {
+        const uint32_t rk = flag[x];
+        const uint32_t nx = x + 1 < len ? flag[x + 1] : nseg;
+        if (nx != rk) seg[rk] = (uint16_t)x;
+      }
+      if (tid == 0) seg[nseg] = (uint16_t)len;
     }
-    if (tid == 0) seg[nseg] = (uint16_t)len;
     __syncthreads();
-    // pairwise merge rounds: segments (2m, 2m+1) -> m, A first on ties
+    // pairwise merge rounds: segments (2m, 2m+1) -> m, A first on ties.
+    // A thread's outputs [x, x1) of one pair start at the merge-path split
+    // (ia, ib); the two heads stay in registers, so a step reads one key.
     uint32_t nsg = nseg;
     K *in = bufA, *out = bufB;
     const uint32_t per = (len + RLM_MT - 1) / RLM_MT;
@@ -948,21 +979,26 @@ __global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const v
         const uint32_t as = seg[2 * m];
         const uint32_t ae = seg[2 * m + 1];
         const uint32_t be = 2 * m + 2 <= nsg ? seg[2 * m + 2] : ae;
-        const uint32_t na = ae - as, nb = be - ae;
-        const K *A = in + as, *B = in + ae;
         const uint32_t rho = x - as;
+        const uint32_t na = ae - as, nb = be - ae;
         uint32_t clo = rho > nb ? rho - nb : 0, chi = rho < na ? rho : na;
         while (clo < chi) {
           const uint32_t mid = (clo + chi) >> 1;
-          if (A[mid] <= B[rho - mid - 1]) clo = mid + 1; else chi = mid;
+          if (in[lpad(as + mid)] <= in[lpad(ae + rho - mid - 1)]) clo = mid + 1; else chi = mid;
         }
-        uint32_t ia = clo, ib = rho - clo;
+        // positions in the buffer of the two heads and the segment ends
+        uint32_t pa = as + clo, pb = ae + (rho - clo);
+        K ha = pa < ae ? in[lpad(pa)] : (K)0, hb = pb < be ? in[lpad(pb)] : (K)0;
         const uint32_t stop = x1 < be ? x1 : be;
         for (; x < stop; ++x) {
-          const bool takeA = ib >= nb || (ia < na && A[ia] <= B[ib]);
-          out[x] = takeA ? A[ia] : B[ib];
-          ia += takeA ? 1u : 0u;
-          ib += takeA ? 0u : 1u;
+          const bool takeA = pb >= be || (pa < ae && ha <= hb);
+          out[lpad(x)] = takeA ? ha : hb;
+          pa += takeA ? 1u : 0u;
+          pb += takeA ? 0u : 1u;
+          const uint32_t pn = takeA ? pa : pb;
+          const K nv = pn < (takeA ? ae : be) ? in[lpad(pn)] : (K)0;
+          ha = takeA ? nv : ha;
+          hb = takeA ? hb : nv;
         }
       }
       __syncthreads();
@@ -983,7 +1019,7 @@ __global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const v
     }
     // keys leave LDS as raw bits at every level (the next level encodes
     // them again on load, as it does the tile sort's output)
-    for (uint32_t x = tid; x < len; x += RLM_MT) dst[C.start + a + x] = Key<KT>::dec(in[x]);
+    for (uint32_t x = tid; x < len; x += RLM_MT) dst[C.start + a + x] = Key<KT>::dec(in[lpad(x)]);
     __syncthreads();
   }
 }
@@ -1189,7 +1225,7 @@ ams_status rlm_typed(const RPlan &pl, const void *in, void *out, void *wsv, hipS
   ams_status st = run_tile_sort(KT, false, in, nullptr, buf(0), nullptr, pl.n, pl.T,
                                 base + pl.o_tile, s);
   if (st) return st;
-  const size_t ldsM = 2 * (size_t)pl.T * sizeof(K) + ((size_t)pl.T + 1) * 2;
+  const size_t ldsM = 2 * (size_t)lpad_size(pl.T) * sizeof(K) + ((size_t)pl.T + 1) * 2;
   (void)hipFuncSetAttribute((const void *)k_rlm_merge<KT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsM);
   for (uint32_t l = 0; l < pl.L; ++l) {
