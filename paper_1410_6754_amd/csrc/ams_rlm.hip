@@ -300,8 +300,14 @@ AMS_DEV uint32_t pivot_draw(const RLev &lv, uint32_t c, uint32_t iter, uint32_t 
   return draw_pos(st, m, total);
 }
 
-// Windows of every selection: the whole of every sequence; the first pivots
-// drawn uniformly from the parent group (whose sequences are consecutive).
+// Windows of every selection: the whole of every sequence.  The first
+// step's pivots (Section 4.1 leaves the choice open): pivot m is the key at
+// the sought rank's proportional position in sequence q_m, drawn uniformly.
+// Where the keys are spread alike over the sequences (every sequence is a
+// sorted tile of the same mix) such a key's rank lies within about
+// N / sqrt(T) of the sought one, so the first step's bracket is some
+// hundred times narrower than that of uniformly drawn keys; any other input
+// only loses that head start.  Later steps draw uniformly from the windows.
 template <int KT>
 __global__ void __launch_bounds__(RLM_NT) k_rlm_sel_init(RWs w, RLev lv, const void *src_) {
   typedef typename Key<KT>::T K;
@@ -320,10 +326,13 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_sel_init(RWs w, RLev lv, const v
       RSel *sp = w.sel + c;
       const uint32_t np = P.size < RLM_M ? P.size : RLM_M;
       if (m < np && C.j != 0) {
-        const uint32_t u = pivot_draw(lv, c, 0, m, P.size);
-        sp->pq[m] = u / lv.T;
-        sp->pt[m] = u % lv.T;
-        sp->pv[m] = (uint64_t)Key<KT>::enc(src[P.start + u]);
+        const uint32_t q = pivot_draw(lv, c, 0, m, S);
+        const uint32_t lq = seq_len(P, q, lv.T);
+        uint32_t t = (uint32_t)(((uint64_t)C.rank * lq) / P.size);
+        t = t < lq ? t : lq - 1;
+        sp->pq[m] = q;
+        sp->pt[m] = t;
+        sp->pv[m] = (uint64_t)Key<KT>::enc(src[P.start + (size_t)q * lv.T + t]);
       }
       if (m == 0) {
         sp->np = np;
