@@ -98,7 +98,7 @@ struct RWs {
   uint32_t *sliceOwner;  // merge slice -> part
   uint32_t *sliceI0, *sliceI1;  // merge slice -> its first piece, one past its last
   uint32_t capCut;
-  uint32_t *scratch;   // per group: part counts (exscan space)
+  uint32_t *scratch;   // per group: five counts (exscan space), 5 (G + 1) entries
 };
 
 AMS_DEV void rlm_error(const RWs &w, uint32_t bits) { atomicOr(&w.hdr->overflow, bits); }
@@ -120,29 +120,58 @@ AMS_DEV uint32_t level_parts(uint32_t N, uint32_t r, uint32_t T) {
 
 // ---------------------------------------------------------------------------
 // Parts of every group: one workgroup of 1024 threads (a level has at most a
-// few ten thousand groups).
+// few ten thousand groups).  The parts of a group share its sequence count
+// S, so their cut, block and piece-offset tables have equal sizes: five
+// exclusive scans over the groups (parts, and the four table sizes) place
+// every part's tables; only the slices differ from part to part.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_rlm_children(RWs w, RLev lv) {
   __shared__ uint32_t tmp[1024 / 64];
   const uint32_t tid = threadIdx.x;
   const uint32_t G = w.hdr->nGroups;
-  uint32_t *pc = w.scratch;  // G + 1 entries
-  for (uint32_t g = tid; g < G; g += 1024)
-    pc[g] = lv.force ? lv.force : level_parts(w.groups[g].size, lv.r, lv.T);
+  // per group (G + 1 entries each): parts, cut entries, selection blocks,
+  // piece offsets, slices
+  uint32_t *pc = w.scratch, *pcut = pc + (G + 1), *pblk = pcut + (G + 1);
+  uint32_t *pq = pblk + (G + 1), *psl = pq + (G + 1);
+  for (uint32_t g = tid; g < G; g += 1024) {
+    const uint32_t N = w.groups[g].size;
+    const uint32_t parts = lv.force ? lv.force : level_parts(N, lv.r, lv.T);
+    const uint32_t S = (N + lv.T - 1) / lv.T;
+    uint32_t sl = 0;
+    for (uint32_t j = 0; j < parts; ++j) {
+      const uint32_t a = (uint32_t)(((uint64_t)j * N) / parts);
+      const uint32_t b = (uint32_t)(((uint64_t)(j + 1) * N) / parts);
+      sl += (b - a + lv.T - 1) / lv.T;
+    }
+    pc[g] = parts;
+    pcut[g] = parts * S;
+    pblk[g] = parts * ((S + RLM_NT - 1) / RLM_NT);
+    pq[g] = parts * (S + 1);
+    psl[g] = sl;
+  }
   __syncthreads();
   const uint32_t nc = block_exscan<1024>(pc, G, tmp);
-  if (nc > lv.capChildren) {
+  uint32_t tot[4];
+  tot[0] = block_exscan<1024>(pcut, G, tmp);
+  tot[1] = block_exscan<1024>(pblk, G, tmp);
+  tot[2] = block_exscan<1024>(pq, G, tmp);
+  tot[3] = block_exscan<1024>(psl, G, tmp);
+  const uint32_t caps[4] = {lv.capCut, lv.capBlk, lv.capQ, lv.capSlice};
+  bool over = nc > lv.capChildren;
+  for (int f = 0; f < 4; ++f) over = over || tot[f] > caps[f];
+  if (over) {
     if (tid == 0) {
-      rlm_error(w, AMS_DEVERR_GROUPS);
+      rlm_error(w, nc > lv.capChildren ? AMS_DEVERR_GROUPS : AMS_DEVERR_TILES);
       w.hdr->nChildren = 0;
     }
     return;
   }
-  // children, with their table sizes in the base fields (scanned below)
   for (uint32_t g = tid; g < G; g += 1024) {
     const RGroup P = w.groups[g];
     const uint32_t parts = lv.force ? lv.force : level_parts(P.size, lv.r, lv.T);
     const uint32_t S = (P.size + lv.T - 1) / lv.T;
+    const uint32_t nbS = (S + RLM_NT - 1) / RLM_NT;
+    uint32_t sl = psl[g];
     for (uint32_t j = 0; j < parts; ++j) {
       const uint32_t a = (uint32_t)(((uint64_t)j * P.size) / parts);
       const uint32_t b = (uint32_t)(((uint64_t)(j + 1) * P.size) / parts);
@@ -153,34 +182,18 @@ __global__ void __launch_bounds__(1024) k_rlm_children(RWs w, RLev lv) {
       c.j = j;
       c.rank = a;
       c.last = j + 1 == parts;
-      c.cutBase = S;
-      c.blkBase = (S + RLM_NT - 1) / RLM_NT;
-      c.qBase = S + 1;
-      c.sliceBase = (c.size + lv.T - 1) / lv.T;
+      c.cutBase = pcut[g] + j * S;
+      c.blkBase = pblk[g] + j * nbS;
+      c.qBase = pq[g] + j * (S + 1);
+      c.sliceBase = sl;
       c.pad[0] = c.pad[1] = 0;
+      sl += (c.size + lv.T - 1) / lv.T;
       w.children[pc[g] + j] = c;
     }
   }
-  __syncthreads();
-  // bases by four exclusive scans over the children
-  uint32_t *cb = (uint32_t *)w.children;
-  const uint32_t stride = sizeof(RGroup) / 4;
-  const uint32_t fields[4] = {offsetof(RGroup, cutBase) / 4, offsetof(RGroup, blkBase) / 4,
-                              offsetof(RGroup, qBase) / 4, offsetof(RGroup, sliceBase) / 4};
-  for (int f = 0; f < 4; ++f) {
-    for (uint32_t c = tid; c < nc; c += 1024) pc[c] = cb[(size_t)c * stride + fields[f]];
-    __syncthreads();
-    const uint32_t tot = block_exscan<1024>(pc, nc, tmp);
-    for (uint32_t c = tid; c < nc; c += 1024) cb[(size_t)c * stride + fields[f]] = pc[c];
-    if (tid == 0) w.hdr->cnt[f] = tot;
-    __syncthreads();
-  }
-  const uint32_t caps[4] = {lv.capCut, lv.capBlk, lv.capQ, lv.capSlice};
-  bool over = false;
-  for (int f = 0; f < 4; ++f) over = over || w.hdr->cnt[f] > caps[f];
   if (tid == 0) {
-    if (over) rlm_error(w, AMS_DEVERR_TILES);
-    w.hdr->nChildren = over ? 0 : nc;
+    for (int f = 0; f < 4; ++f) w.hdr->cnt[f] = tot[f];
+    w.hdr->nChildren = nc;
   }
 }
 
@@ -1167,7 +1180,7 @@ ams_status make_rlm_plan(RPlan &pl, ams_key_t t, uint64_t n, const ams_rlm_param
   pl.o_si0 = take((size_t)pl.maxSlice * 4);
   pl.o_si1 = take((size_t)pl.maxSlice * 4);
   pl.o_q = take((size_t)pl.maxQ * 4);
-  pl.o_scr = take((ng + 1) * 4);
+  pl.o_scr = take(5 * (ng + 1) * 4);
   pl.bytes = o;
   return AMS_OK;
 }
@@ -1322,7 +1335,7 @@ ams_status step_select_typed(const void *d_runs, uint64_t n, uint32_t T, uint32_
   pl.o_bl = take((RLM_M + 1) * blk * 4);
   pl.o_bown = take(blk * 4);
   pl.o_sown = take((S + parts) * 4);
-  pl.o_scr = take((parts + 2) * 4);
+  pl.o_scr = take(5 * 2 * 4);  // one group
   void *ws = nullptr;
   if (hipMallocAsync(&ws, o, s) != hipSuccess) {
     set_error("hipMallocAsync(%zu) failed", o);
