@@ -853,29 +853,32 @@ AMS_DEV uint32_t upper_le(const uint32_t *v, uint32_t n, uint32_t x) {
   return lo;
 }
 
-// Key slots of the merge buffers: one spare slot after every 16 keys, so
-// threads that work on runs of keys 4 to 8 apart (as the merge rounds'
-// threads do) meet in different LDS banks.
-AMS_DEV uint32_t lpad(uint32_t x) { return x + (x >> 4); }
-AMS_HD uint32_t lpad_size(uint32_t T) { return T + (T >> 4); }
+// Key slots of the merge buffer: one spare slot after every 8 keys.  A
+// thread's 8 outputs of a merge round (keys 8t .. 8t+7) then sit in 8
+// consecutive slots, and threads whose runs lie 4 to 8 keys apart meet in
+// different LDS banks.
+AMS_DEV uint32_t lpad(uint32_t x) { return x + (x >> 3); }
+AMS_HD uint32_t lpad_size(uint32_t T) { return T + (T >> 3); }
 
 template <int KT>
-__global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const void *src_,
+__global__ void __launch_bounds__(RLM_MT, 6) k_rlm_merge(RWs w, RLev lv, const void *src_,
                                                          void *dst_) {
   typedef typename Key<KT>::T K;
   constexpr uint32_t PT = RLM_TMAX / RLM_MT;  // keys per thread and slice
+  constexpr uint32_t NW = RLM_MT / 64;
   const GMem<K> *src = (const GMem<K> *)src_;
   GMem<K> *dst = (GMem<K> *)dst_;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const uint32_t T = lv.T;
-  K *bufA = (K *)smem_raw;
-  K *bufB = bufA + lpad_size(T);
-  // segment starts relative to the slice (< T, so 16 bits): first the
-  // pieces' offsets, then the merge's segments
-  uint16_t *seg = (uint16_t *)(bufB + lpad_size(T));  // T + 1 entries
-  __shared__ uint32_t tmp[RLM_MT / 64];
+  // the slice, merged in place (a round's outputs wait in registers until
+  // every thread has read its inputs), and two segment lists (the current
+  // round's and the next one's), T + 1 starts relative to the slice each
+  K *buf = (K *)smem_raw;
+  uint16_t *segA = (uint16_t *)(buf + lpad_size(T));
+  uint16_t *segB = segA + (T + 1);
+  __shared__ uint32_t ccount[PT * NW];  // piece starts per 64 keys (many pieces)
   __shared__ uint32_t shd[2];
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t ns = w.hdr->cnt[3];
   for (uint32_t item = blockIdx.x; item < ns; item += gridDim.x) {
     const RGroup C = w.children[w.sliceOwner[item]];
@@ -899,30 +902,29 @@ __global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const v
     if (cached)
       for (uint32_t k = tid; k <= np; k += RLM_MT) {
         const uint32_t q = Q[i0 + k];
-        seg[k] = (uint16_t)(q > a ? (q - a < len ? q - a : len) : 0u);
+        segA[k] = (uint16_t)(q > a ? (q - a < len ? q - a : len) : 0u);
       }
     if (tid == 0) shd[0] = a - Q[i0];
     __syncthreads();
     const uint32_t lead = shd[0];
-    // gather: key x of the slice comes from the piece holding a + x; the
-    // piece searches first, then all loads in flight together
-    uint32_t *flag = (uint32_t *)bufB;  // piece starts, when too many pieces for seg
-    uint32_t pi[PT], pp[PT];
-    bool ok[PT];
+    // gather: key x of the slice comes from the piece holding a + x; each
+    // key's load is issued as soon as its piece is found, all in flight
+    // together before the first is stored
+    K v[PT];
+    bool st[PT];
 #pragma unroll
     for (uint32_t u = 0; u < PT; ++u) {
       const uint32_t x = tid + u * RLM_MT;
-      ok[u] = x < len;
       uint32_t k = 0, rel = 0;
-      if (ok[u]) {
+      if (x < len) {
         if (cached) {
           uint32_t l = 0, h = np;  // last k with seg[k] <= x
           while (h - l > 1) {
             const uint32_t m = (l + h) >> 1;
-            if (seg[m] <= x) l = m; else h = m;
+            if (segA[m] <= x) l = m; else h = m;
           }
           k = l;
-          rel = seg[k];
+          rel = segA[k];
         } else {
           k = upper_le<K>(Q + i0, np, a + x);
           rel = Q[i0 + k] > a ? Q[i0 + k] - a : 0u;
@@ -932,22 +934,16 @@ __global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const v
       // position in sequence i: the piece's cut plus the keys of the piece
       // before x (the first piece also counts those before the slice)
       const uint32_t pos = cut[i] + (x - rel) + (k == 0 ? lead : 0u);
-      pi[u] = i;
-      pp[u] = pos;
-      ok[u] = ok[u] && pos < seq_len(P, i, T);
-      if (x < len && !ok[u]) rlm_error(w, AMS_DEVERR_RANGE);  // cannot happen
-      if (!cached && x < len) flag[x] = (x == 0 || (k != 0 && rel == x)) ? 1u : 0u;
+      st[u] = x < len && (x == 0 || (k != 0 && rel == x));  // a piece starts here
+      const bool ok = x < len && pos < seq_len(P, i, T);
+      if (x < len && !ok) rlm_error(w, AMS_DEVERR_RANGE);  // cannot happen
+      v[u] = ok ? Key<KT>::enc(src[P.start + (size_t)i * T + pos]) : (K)0;
     }
-    K v[PT];
+    // slot of key tid + u RLM_MT: lpad(tid) + u (RLM_MT + RLM_MT / 8)
+    K *gb = buf + lpad(tid);
 #pragma unroll
     for (uint32_t u = 0; u < PT; ++u)
-      v[u] = ok[u] ? Key<KT>::enc(src[P.start + (size_t)pi[u] * T + pp[u]]) : (K)0;
-#pragma unroll
-    for (uint32_t u = 0; u < PT; ++u) {
-      const uint32_t x = tid + u * RLM_MT;
-      if (x < len) bufA[lpad(x)] = v[u];
-    }
-    __syncthreads();
+      if (tid + u * RLM_MT < len) gb[u * (RLM_MT + RLM_MT / 8)] = v[u];
     uint32_t nseg;
     if (cached) {
       // the merge's segments are the non-empty pieces: their starts,
@@ -956,92 +952,120 @@ __global__ void __launch_bounds__(RLM_MT, 2) k_rlm_merge(RWs w, RLev lv, const v
         uint32_t base = 0;
         for (uint32_t k0 = 0; k0 < np; k0 += 64) {
           const uint32_t k = k0 + tid;
-          const uint32_t s0 = k < np ? seg[k] : 0u, s1 = k < np ? seg[k + 1] : 0u;
+          const uint32_t s0 = k < np ? segA[k] : 0u, s1 = k < np ? segA[k + 1] : 0u;
           const bool keep = k < np && s1 > s0;
           const uint64_t mk = ballot(keep);
-          if (keep) seg[base + bits_below(mk)] = (uint16_t)s0;
+          if (keep) segA[base + bits_below(mk)] = (uint16_t)s0;
           base += (uint32_t)__builtin_popcountll(mk);
         }
         if (tid == 0) {
-          seg[base] = (uint16_t)len;
+          segA[base] = (uint16_t)len;
           shd[1] = base;
         }
       }
       __syncthreads();
       nseg = shd[1];
     } else {
-      nseg = block_exscan<RLM_MT>(flag, len, tmp);
-      // flag[] now holds ranks; a start is where the rank steps
-      for (uint32_t x = tid; x < len; x += RLM_MT) {
-        const uint32_t rk = flag[x];
-        const uint32_t nx = x + 1 < len ? flag[x + 1] : nseg;
-        if (nx != rk) seg[rk] = (uint16_t)x;
+      // the piece starts in key order: ballots per 64 keys, then each 64
+      // keys' offset among all starts (chunk (u, wave) holds keys
+      // [u * RLM_MT + 64 wave, + 64))
+      uint64_t mk[PT];
+#pragma unroll
+      for (uint32_t u = 0; u < PT; ++u) {
+        mk[u] = ballot(st[u]);
+        if (lane == 0) ccount[u * NW + wave] = (uint32_t)__builtin_popcountll(mk[u]);
       }
-      if (tid == 0) seg[nseg] = (uint16_t)len;
+      __syncthreads();
+      nseg = 0;
+      uint32_t before[PT];
+#pragma unroll
+      for (uint32_t u = 0; u < PT; ++u) before[u] = 0;
+      for (uint32_t j = 0; j < PT * NW; ++j) {
+        const uint32_t c = ccount[j];
+#pragma unroll
+        for (uint32_t u = 0; u < PT; ++u) before[u] += j < u * NW + wave ? c : 0u;
+        nseg += c;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < PT; ++u)
+        if (st[u]) segA[before[u] + bits_below(mk[u])] = (uint16_t)(tid + u * RLM_MT);
+      if (tid == 0) segA[nseg] = (uint16_t)len;
     }
     __syncthreads();
     // pairwise merge rounds: segments (2m, 2m+1) -> m, A first on ties.
-    // A thread's outputs [x, x1) of one pair start at the merge-path split
-    // (ia, ib); the two heads stay in registers, so a step reads one key.
+    // Thread outputs [x0, x1): the pair holding x0 and the merge-path split
+    // (pa, pb) of its two segments; both heads stay in registers, so a step
+    // reads one key; where the range reaches the next pair, that pair
+    // starts at its beginning.
     uint32_t nsg = nseg;
-    K *in = bufA, *out = bufB;
-    const uint32_t per = (len + RLM_MT - 1) / RLM_MT;
+    uint16_t *sin = segA, *sout = segB;
+    const uint32_t x0 = tid * PT < len ? tid * PT : len;  // outputs [x0, x1)
+    const uint32_t x1 = x0 + PT < len ? x0 + PT : len;
+    K *ob = buf + lpad(x0);  // their slots: ob[0 .. x1 - x0)
     while (nsg > 1) {
-      const uint32_t x0 = tid * per < len ? tid * per : len;
-      const uint32_t x1 = x0 + per < len ? x0 + per : len;
-      uint32_t x = x0;
-      while (x < x1) {
-        // pair m holding output x: segments 2m, 2m+1
+      K o[PT];
+#pragma unroll
+      for (uint32_t k = 0; k < PT; ++k) o[k] = (K)0;
+      if (x0 < x1) {
         uint32_t l = 0, h = (nsg + 1) / 2;  // pairs
         while (h - l > 1) {
           const uint32_t m = (l + h) >> 1;
-          if (seg[2 * m] <= x) l = m; else h = m;
+          if (sin[2 * m] <= x0) l = m; else h = m;
         }
-        const uint32_t m = l;
-        const uint32_t as = seg[2 * m];
-        const uint32_t ae = seg[2 * m + 1];
-        const uint32_t be = 2 * m + 2 <= nsg ? seg[2 * m + 2] : ae;
-        const uint32_t rho = x - as;
+        uint32_t m = l;
+        uint32_t as = sin[2 * m], ae = sin[2 * m + 1];
+        uint32_t be = 2 * m + 2 <= nsg ? sin[2 * m + 2] : ae;
+        const uint32_t rho = x0 - as;
         const uint32_t na = ae - as, nb = be - ae;
         uint32_t clo = rho > nb ? rho - nb : 0, chi = rho < na ? rho : na;
         while (clo < chi) {
           const uint32_t mid = (clo + chi) >> 1;
-          if (in[lpad(as + mid)] <= in[lpad(ae + rho - mid - 1)]) clo = mid + 1; else chi = mid;
+          if (buf[lpad(as + mid)] <= buf[lpad(ae + rho - mid - 1)]) clo = mid + 1; else chi = mid;
         }
-        // positions in the buffer of the two heads and the segment ends
         uint32_t pa = as + clo, pb = ae + (rho - clo);
-        K ha = pa < ae ? in[lpad(pa)] : (K)0, hb = pb < be ? in[lpad(pb)] : (K)0;
-        const uint32_t stop = x1 < be ? x1 : be;
-        for (; x < stop; ++x) {
-          const bool takeA = pb >= be || (pa < ae && ha <= hb);
-          out[lpad(x)] = takeA ? ha : hb;
-          pa += takeA ? 1u : 0u;
-          pb += takeA ? 0u : 1u;
-          const uint32_t pn = takeA ? pa : pb;
-          const K nv = pn < (takeA ? ae : be) ? in[lpad(pn)] : (K)0;
-          ha = takeA ? nv : ha;
-          hb = takeA ? hb : nv;
+        K ha = pa < ae ? buf[lpad(pa)] : (K)0, hb = pb < be ? buf[lpad(pb)] : (K)0;
+#pragma unroll
+        for (uint32_t k = 0; k < PT; ++k) {
+          const uint32_t x = x0 + k;
+          if (x < x1) {
+            if (x == be) {  // the next pair, from its beginning
+              ++m;
+              as = be;
+              ae = sin[2 * m + 1];
+              be = 2 * m + 2 <= nsg ? sin[2 * m + 2] : ae;
+              pa = as;
+              pb = ae;
+              ha = pa < ae ? buf[lpad(pa)] : (K)0;
+              hb = pb < be ? buf[lpad(pb)] : (K)0;
+            }
+            const bool takeA = pb >= be || (pa < ae && ha <= hb);
+            o[k] = takeA ? ha : hb;
+            pa += takeA ? 1u : 0u;
+            pb += takeA ? 0u : 1u;
+            const uint32_t pn = takeA ? pa : pb;
+            const K nv = pn < (takeA ? ae : be) ? buf[lpad(pn)] : (K)0;
+            ha = takeA ? nv : ha;
+            hb = takeA ? hb : nv;
+          }
         }
       }
-      __syncthreads();
-      // segments of the next round: every other boundary
       const uint32_t nn = (nsg + 1) / 2;
-      uint32_t sv[8];
-      uint32_t cntv = 0;
-      for (uint32_t k = tid; k < nn && cntv < 8; k += RLM_MT) sv[cntv++] = seg[2 * k];
-      __syncthreads();
-      cntv = 0;
-      for (uint32_t k = tid; k < nn && cntv < 8; k += RLM_MT) seg[k] = (uint16_t)sv[cntv++];
-      if (tid == 0) seg[nn] = (uint16_t)len;
+      __syncthreads();  // every input read
+#pragma unroll
+      for (uint32_t k = 0; k < PT; ++k)
+        if (x0 + k < x1) ob[k] = o[k];
+      // segments of the next round: every other boundary
+      for (uint32_t k = tid; k < nn; k += RLM_MT) sout[k] = sin[2 * k];
+      if (tid == 0) sout[nn] = (uint16_t)len;
       __syncthreads();
       nsg = nn;
-      K *t = in;
-      in = out;
-      out = t;
+      uint16_t *t = sin;
+      sin = sout;
+      sout = t;
     }
     // keys leave LDS as raw bits at every level (the next level encodes
     // them again on load, as it does the tile sort's output)
-    for (uint32_t x = tid; x < len; x += RLM_MT) dst[C.start + a + x] = Key<KT>::dec(in[lpad(x)]);
+    for (uint32_t x = tid; x < len; x += RLM_MT) dst[C.start + a + x] = Key<KT>::dec(buf[lpad(x)]);
     __syncthreads();
   }
 }
@@ -1247,7 +1271,7 @@ ams_status rlm_typed(const RPlan &pl, const void *in, void *out, void *wsv, hipS
   ams_status st = run_tile_sort(KT, false, in, nullptr, buf(0), nullptr, pl.n, pl.T,
                                 base + pl.o_tile, s);
   if (st) return st;
-  const size_t ldsM = 2 * (size_t)lpad_size(pl.T) * sizeof(K) + ((size_t)pl.T + 1) * 2;
+  const size_t ldsM = (size_t)lpad_size(pl.T) * sizeof(K) + 2 * ((size_t)pl.T + 1) * 2;
   (void)hipFuncSetAttribute((const void *)k_rlm_merge<KT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsM);
   for (uint32_t l = 0; l < pl.L; ++l) {

@@ -112,3 +112,23 @@ def test_step_multiselect_unsorted_runs_stay_in_bounds(api, n, run_keys, parts):
     seqs = [[int(v) for v in ords[a:a + run_keys]] for a in range(0, n, run_keys)]
     want = np.array(orlm.rlm_splits(seqs, parts), dtype=np.uint32)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("kt", [U64, U32])
+def test_rlm_slice_spanning_many_empty_pieces(api, kt):
+    """A slice whose pieces lie far apart in sequence order: tiles of 64 keys,
+    the smallest keys in tile 0 (one key) and in tiles 100.., none in tiles
+    1..99, so the first part's first slice spans 101 pieces of which 99 are
+    empty, more pieces than a tile holds keys (the merge then finds the
+    pieces in the global piece offsets and compacts their starts by
+    ballots)."""
+    rng = np.random.default_rng([W.BASE_SEED, 790 + kt])
+    dt = np.uint64 if kt == U64 else np.uint32
+    T, n = 64, 64 * 200
+    keys = rng.integers(1000, 2000, n).astype(dt)       # large keys everywhere
+    small = rng.integers(1, 100, n).astype(dt)
+    keys[0] = 0                                         # the smallest key, in tile 0
+    keys[100 * T:113 * T] = small[100 * T:113 * T]      # tiles 100..112 all small
+    p = api.rlm_params(ways=16, tile_keys=T)
+    log("rlm slice over 101 pieces kt=%d" % kt)
+    check_rlm(api, kt, keys, params=p, what="rlm many empty pieces")
