@@ -798,22 +798,23 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_cut(RWs w, RLev lv) {
 }
 
 // Piece offsets of every part: Q[i] = keys of the part in sequences < i.
-__global__ void __launch_bounds__(RLM_NT) k_rlm_pieces(RWs w, RLev lv) {
-  __shared__ uint32_t tmp[RLM_NT / 64];
+template <uint32_t NT>
+__global__ void __launch_bounds__(NT) k_rlm_pieces(RWs w, RLev lv) {
+  __shared__ uint32_t tmp[NT / 64];
   const uint32_t nc = w.hdr->nChildren;
   for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
     const RGroup C = w.children[c];
     const RGroup P = w.groups[C.parent];
     const uint32_t S = (P.size + lv.T - 1) / lv.T;
     uint32_t *Q = w.q + C.qBase;
-    for (uint32_t i = threadIdx.x; i < S; i += RLM_NT) {
+    for (uint32_t i = threadIdx.x; i < S; i += NT) {
       const uint32_t a = w.cut[C.cutBase + i];
       // the next part's cut row follows this one (same parent, same S)
       const uint32_t b = C.last ? seq_len(P, i, lv.T) : w.cut[C.cutBase + S + i];
       Q[i] = b >= a ? b - a : 0u;
     }
     __syncthreads();
-    const uint32_t tot = block_exscan<RLM_NT>(Q, S, tmp);
+    const uint32_t tot = block_exscan<NT>(Q, S, tmp);
     if (threadIdx.x == 0) {
       Q[S] = tot;
       if (tot != C.size) rlm_error(w, AMS_DEVERR_RANGE);
@@ -823,7 +824,7 @@ __global__ void __launch_bounds__(RLM_NT) k_rlm_pieces(RWs w, RLev lv) {
     // the pieces each slice of T keys overlaps: slice k starts in the piece
     // holding key k*T and ends in the piece holding its last key
     const uint32_t nsl = (C.size + lv.T - 1) / lv.T;
-    for (uint32_t i = threadIdx.x; i < S; i += RLM_NT) {
+    for (uint32_t i = threadIdx.x; i < S; i += NT) {
       const uint32_t qa = Q[i], qb = Q[i + 1];
       if (qa >= qb) continue;  // empty piece
       for (uint32_t k = (qa + lv.T - 1) / lv.T; k < nsl && k * lv.T < qb; ++k)
@@ -1302,8 +1303,14 @@ ams_status rlm_typed(const RPlan &pl, const void *in, void *out, void *wsv, hipS
     }
     {
       TraceScope ts("rlm_pieces", l, s);
-      hipLaunchKernelGGL(k_rlm_pieces, dim3(grid_cap(pl.maxChildren, 2048)), dim3(RLM_NT), 0, s,
-                         w, lv);
+      // wide groups (up to 65,536 sequences at the first level) scan with
+      // 1024 threads per part
+      if (pl.maxS[l] > 4096)
+        hipLaunchKernelGGL(k_rlm_pieces<1024>, dim3(grid_cap(pl.maxChildren, 2048)), dim3(1024), 0,
+                           s, w, lv);
+      else
+        hipLaunchKernelGGL(k_rlm_pieces<RLM_NT>, dim3(grid_cap(pl.maxChildren, 2048)),
+                           dim3(RLM_NT), 0, s, w, lv);
     }
     {
       TraceScope ts("rlm_merge", l, s);
