@@ -945,6 +945,7 @@ __global__ void __launch_bounds__(RLM_MT, 6) k_rlm_merge(RWs w, RLev lv, const v
 #pragma unroll
     for (uint32_t u = 0; u < PT; ++u)
       if (tid + u * RLM_MT < len) gb[u * (RLM_MT + RLM_MT / 8)] = v[u];
+    __syncthreads();  // every piece search done before the piece list is compacted
     uint32_t nseg;
     if (cached) {
       // the merge's segments are the non-empty pieces: their starts,

@@ -144,3 +144,19 @@ def test_rlm_2p20_matches_oracle(api):
     want, _ = oracle.oracle_sort(kt, keys)
     got = host(api.rlm_sort_keys(to_dev(keys), params=api.rlm_params(**pkw)))
     assert_same_bits(got, want, "rlm 2^20")
+
+
+@pytest.mark.parametrize("dist", ["zipf", "few", "sorted", "equal"])
+def test_rlm_2p24_skewed_matches_oracle(api, dist):
+    """RLM-sort of 2^24 + odd uint64 keys at four levels' depth (tiles of 4096,
+    r = 16) on skewed inputs: Zipf(1.1), 2^10 distinct values, sorted and
+    all equal. The first round's pivots assume tiles of the same mix; here
+    they do not, and only the number of selection rounds may change."""
+    n = (1 << 24) + 4097
+    keys = W.keys(W.KEY_U64, n, W.rng_for(30), dist)
+    log("oracle: rlm %s 2^24+ on %d threads" % (dist, threads()))
+    perm = oracle.oracle_sort_perm_parallel(W.KEY_U64, keys, threads())
+    want = keys[perm.astype(np.int64)]
+    log("rlm %s 2^24+ on the GPU" % dist)
+    got = host(api.rlm_sort_keys(to_dev(keys)))
+    assert_same_bits(got, want, "rlm " + dist)
