@@ -63,15 +63,19 @@ def key_bytes(kt: int) -> int:
     return 8 if kt == W.KEY_U64 else 4
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=("ams_engine.hip", "ams_device.h")) -> str:
     h = hashlib.sha256()
-    for f in ("ams_engine.hip", "ams_device.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1410_6754_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
+# the sources of RLM-sort's merge kernel
+RLM_SOURCES = ("ams_rlm.hip", "ams_device.h")
+
+
+def measured_traffic(kernel: str, workload: str, files=("ams_engine.hip", "ams_device.h")):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -80,7 +84,7 @@ def measured_traffic(kernel: str, workload: str):
     try:
         d = json.load(open(path))
         e = d[workload][kernel]
-        if e.get("source_hash") != kernel_source_hash():
+        if e.get("source_hash") != kernel_source_hash(files):
             return None
         return e["bytes_per_launch"]
     except Exception:
@@ -540,8 +544,8 @@ def bench_rlm(args) -> int:
         achieved = 2 * w * n / (am * 1e-3) / 1e9
         roof = {"kernel": "rlm_merge", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "algorithmic_bytes_per_launch": 2 * w * n,
-                "avg_launch_ms": round(am, 4)}
+                "traffic": measured_traffic("rlm_merge", args.workload, RLM_SOURCES),
+                "algorithmic_bytes_per_launch": 2 * w * n, "avg_launch_ms": round(am, 4)}
     else:
         roof = None
     line = {

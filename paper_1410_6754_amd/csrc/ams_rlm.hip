@@ -1066,8 +1066,14 @@ __global__ void __launch_bounds__(RLM_MT, 6) k_rlm_merge(RWs w, RLev lv, const v
       sout = t;
     }
     // keys leave LDS as raw bits at every level (the next level encodes
-    // them again on load, as it does the tile sort's output)
-    for (uint32_t x = tid; x < len; x += RLM_MT) dst[C.start + a + x] = Key<KT>::dec(buf[lpad(x)]);
+    // them again on load, as it does the tile sort's output).  The loop
+    // starts sh keys before the slice, at a 128-byte line, so that every
+    // wavefront stores whole lines (only the slice's first and last lines
+    // are shared with its neighbours).
+    constexpr uint32_t LK = 128 / sizeof(K);  // keys per 128-byte line
+    const uint32_t sh = (uint32_t)((C.start + a) & (LK - 1u));
+    for (uint32_t y = tid; y < len + sh; y += RLM_MT)
+      if (y >= sh) dst[C.start + a + (y - sh)] = Key<KT>::dec(buf[lpad(y - sh)]);
     __syncthreads();
   }
 }
