@@ -1101,7 +1101,9 @@ __global__ void __launch_bounds__(256) k_pack(Ws w, Lev lv, LevTable lt) {
           ps.leafKeys[LEAF_COPY] += size;
         }
       }
-      gD[c] = (uint8_t)(cd | (p.kind[c] << 4));
+      // high bits: decode on the way out, for final children written to the
+      // output only (keys in TMP stay encoded; their copy leaf decodes them)
+      gD[c] = (uint8_t)(cd | ((p.kind[c] != CHILD_REG && cd == BUF_OUT) ? (1u << 4) : 0u));
     }
     // statistics: leaves, the largest regular child, keys in final children
     // and the imbalance L* / ceil(W / r) of the grouping (Section 6, lemma on

@@ -208,3 +208,36 @@ def test_stratified_splitters_large_with_stats(api):
     want, _ = oracle.oracle_sort(U64, keys)
     assert np.array_equal(out, want)
     assert st["levels"] == 2 and st["keys"][1] == n and st["imbalance_max"][1] >= 1.0
+
+
+# Final children (equality buckets) of a subproblem read from the output
+# buffer (the middle level of three, or any level of an in-place sort) go
+# through the temporary buffer and a copy leaf: float keys must be decoded
+# exactly once on the way to the output.
+@pytest.mark.parametrize("kt", [F32, U64])
+@pytest.mark.parametrize("dist", ["few", "zipf", "specials"])
+@pytest.mark.parametrize("levels,k,b", [(3, 16, 2), (3, 64, 1)])
+def test_final_children_through_temp(api, kt, dist, levels, k, b):
+    n = 400_003
+    keys = gen(kt, n, dist, 860)
+    p = api.make_params(levels=levels, k=k, overpartition_b=b)
+    log("final children via temp kt=%d %s levels=%d k=%d b=%d" % (kt, dist, levels, k, b))
+    check_sort_keys(api, kt, keys, params=p, what="%s levels %d" % (dist, levels))
+
+
+@pytest.mark.parametrize("dist", ["few", "zipf", "specials"])
+def test_in_place_float_duplicates(api, dist):
+    import oracle
+    keys = gen(F32, 300_001, dist, 870)
+    d = to_dev(keys)
+    log("in place f32 %s" % dist)
+    api.sort_keys(d, out=d)
+    want, _ = oracle.oracle_sort(F32, keys)
+    from gpu_util import assert_same_bits
+    assert_same_bits(to_host(d), want, "in place f32 " + dist)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    dk, dv = to_dev(keys), to_dev(vals)
+    api.sort_pairs(dk, dv, out_keys=dk, out_vals=dv)
+    wk, wv = oracle.oracle_sort(F32, keys, vals)
+    assert_same_bits(to_host(dk), wk, "in place f32 pairs " + dist)
+    assert np.array_equal(to_host(dv), wv)
