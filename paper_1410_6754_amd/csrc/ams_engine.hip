@@ -51,6 +51,8 @@ struct Ctr {
   uint32_t nmerge;               // ranges the merge fallback sorted
   uint32_t nbl;                  // entries of the oversized-leaf list
   uint32_t nrest;                // entries of the remainder list (k_big_rest)
+  uint32_t finNext;              // leaves k_finish handed out after the first gridDim.x
+  uint32_t pad0;
   unsigned long long lv_keys[MAXLEV];     // keys in the partitioned subproblems
   unsigned long long lv_final[MAXLEV];    // keys placed in final children
   unsigned long long lv_imb_sum[MAXLEV];  // sum of the ratio over subproblems
@@ -1974,7 +1976,8 @@ template <int KT, bool PAY>
 AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
                       const typename Key<KT>::T *src_, const uint32_t *vsrc_, bool enc_in,
                       typename Key<KT>::T *dst_, uint32_t *vdst_, bool dec_out, uint32_t s,
-                      uint32_t C, uint32_t cutoff, uint64_t st, bool sampled_only) {
+                      uint32_t C, uint32_t cutoff, uint64_t st, bool sampled_only,
+                      uint32_t *nextSlot = nullptr, uint32_t nextVal = 0) {
   typedef typename Key<KT>::T K;
   // global views of the leaf's buffers: global (not flat) loads and stores
   // count only in vmcnt, so the LDS waits of the ranking never wait for them
@@ -2010,6 +2013,9 @@ AMS_DEV void lds_sort(const FinSmem<typename Key<KT>::T> &sm,
     xk[k] = enc_in ? Key<KT>::enc(x) : x;
     if (PAY) xv[k] = valid ? vsrc[p] : 0u;
   }
+  // the caller's next leaf, requested before these loads: published once
+  // they are in, when its request has long been answered
+  if (nextSlot && tid == 0) *nextSlot = gridDim.x + nextVal;
 
   // Bucket counts, their exclusive scan (bstart) and the largest bucket for
   // ids xir[k] of the valid slots.  Keys only: slot = LDS atomic (the
@@ -2923,25 +2929,38 @@ __global__ void __launch_bounds__(FIN_THREADS, PAY ? 2 : 4) k_finish(Ws w, uint3
   const uint32_t tid = threadIdx.x;
   uint32_t nleaf = w.ctr->nleaf;
   if (nleaf > w.capLeaf) nleaf = w.capLeaf;
-  for (uint32_t li = blockIdx.x; li < nleaf; li += gridDim.x) {
+  // Leaves differ in size: after its first leaf a workgroup takes the next
+  // unclaimed one from a counter, so the leaves still go out in list order
+  // (neighbouring leaves side by side, as with a stride) but no workgroup
+  // ends far behind the others.  The next index is requested as a leaf
+  // starts and published by lds_sort once the leaf's keys are in.
+  __shared__ uint32_t sNext;
+  uint32_t li = blockIdx.x;
+  while (li < nleaf) {
     const Seg L = w.leaves[li];
+    uint32_t nx = 0;  // leaves handed out after the first gridDim.x, before this request
+    if (tid == 0) nx = atomicInc(&w.ctr->finNext, 0xFFFFFFFFu);
     const Root R = w.roots[L.root];
     const uint32_t kind = seg_kind(L.meta), buf = seg_buf(L.meta);
     // defensive: never touch memory outside the root, nor more than C keys
-    if ((uint64_t)L.off + L.size > R.n || (kind == LEAF_REG && L.size > C) || kind == LEAF_BIG) {
-      if (tid == 0) raise_error(w.ctr, 32u);
-      continue;
-    }
+    const bool bad =
+        (uint64_t)L.off + L.size > R.n || (kind == LEAF_REG && L.size > C) || kind == LEAF_BIG;
     const K *src = kptr<K>(w, R, buf) + L.off;
     const uint32_t *vsrc = PAY ? vptr(w, R, buf) + L.off : nullptr;
     K *dst = (K *)R.kout + L.off;
     uint32_t *vdst = PAY ? R.vout + L.off : nullptr;
-    if (kind == LEAF_COPY) {
-      copy_range<KT, PAY>(src, vsrc, dst, vdst, L.size);
-      continue;
+    if (bad || kind == LEAF_COPY) {
+      if (bad && tid == 0) raise_error(w.ctr, 32u);
+      if (!bad) copy_range<KT, PAY>(src, vsrc, dst, vdst, L.size);
+      if (tid == 0) sNext = gridDim.x + nx;
+    } else {
+      lds_sort<KT, PAY>(sm, src, vsrc, buf == BUF_IN, dst, vdst, true, L.size, C, cutoff,
+                        stream_state(seed, LEAF_STREAM, L.root, L.off), sampled_only, &sNext,
+                        nx);
     }
-    lds_sort<KT, PAY>(sm, src, vsrc, buf == BUF_IN, dst, vdst, true, L.size, C, cutoff,
-                      stream_state(seed, LEAF_STREAM, L.root, L.off), sampled_only);
+    __syncthreads();
+    li = sNext;
+    __syncthreads();  // every thread has read sNext before thread 0 writes it again
   }
 }
 
