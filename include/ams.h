@@ -407,7 +407,9 @@ ams_status ams_step_multiselect(ams_key_t t, const void *d_runs, size_t n, uint3
 
 /* Bucket grouping alone (Section 6 and its lemma; Appendix C): w[0..nb)
  * weights -> d_out[0] = optimal maximum load L*, d_out[1] = number of groups
- * g, d_out[2..2+g) = start index of each greedy group under L*.  nb <= 4095. */
+ * g, d_out[2..2+g) = start index of each greedy group under L*.  nb <= 4095;
+ * the weights must sum to less than 2^32 (as bucket sizes of one subproblem
+ * do); d_out holds nb + 2 words. */
 ams_status ams_step_pack(const uint32_t *d_w, uint32_t nb, uint32_t r, uint32_t *d_out,
                          void *stream);
 

@@ -779,7 +779,12 @@ AMS_DEV uint32_t optimal_load(const uint32_t *wgt, uint32_t nb, uint32_t r, uint
   __syncthreads();
   if (Wout) *Wout = W;
   uint32_t avg = (uint32_t)(((uint64_t)W + r - 1) / r);
-  uint32_t lo = max(mx, avg), hi = avg + mx;
+  // L* <= avg + mx (under that load every group the greedy closes holds more
+  // than avg, so there are at most r) and L* <= W (one group holds all); the
+  // sum is formed in 64 bits: with few groups and one heavy bucket it can
+  // pass 2^32 while W cannot
+  uint32_t lo = max(mx, avg);
+  uint32_t hi = (uint32_t)min((uint64_t)avg + mx, (uint64_t)W);
   while (lo < hi) {
     uint32_t span = hi - lo;
     bool active;

@@ -105,6 +105,10 @@ def test_pack(api):
         cases.append((w, r))
     cases.append((np.zeros(10, np.uint32), 3))
     cases.append((np.array([5], np.uint32), 1))
+    # ceil(W/r) + the largest bucket passes 2^32 while W does not
+    cases.append((np.array([2 ** 30, 2 ** 31 + 2 ** 20, 2 ** 30 - 2 ** 21], np.uint32), 2))
+    cases.append((np.array([2 ** 31, 2 ** 31 - 1], np.uint32), 1))
+    cases.append((np.array([2 ** 20, 2 ** 32 - 2 ** 21, 0, 2 ** 19], np.uint32), 3))
     for w, r in cases:
         L, starts = steps.pack([int(v) for v in w], r)
         out = to_host(api.step_pack(torch.from_numpy(w).cuda(), r))

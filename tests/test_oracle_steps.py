@@ -107,6 +107,17 @@ def test_pack_optimal_against_exhaustive_enumeration():
         assert max(sum(w[a:b]) for a, b in zip(starts, ends)) <= L
 
 
+def test_pack_weights_near_2_to_32():
+    # few groups and one heavy bucket: ceil(W/r) + the largest bucket passes
+    # 2^32 while W does not; the optimum is worked out by hand
+    w = [2 ** 30, 2 ** 31 + 2 ** 20, 2 ** 30 - 2 ** 21]
+    L, starts = steps.pack(w, 2)
+    assert L == steps.pack_bruteforce(w, 2) == 3 * 2 ** 30 - 2 ** 20
+    assert starts == [0, 1]
+    w = [2 ** 31, 2 ** 31 - 1]
+    assert steps.pack(w, 1) == (2 ** 32 - 1, [0])
+
+
 def test_pack_greedy_is_maximal():
     w = [3, 1, 4, 1, 5, 9, 2, 6, 5, 3]
     L, starts = steps.pack(w, 3)
