@@ -7,11 +7,15 @@ element against the oracle (its parallel mergesort on the host's cores).
 * 2^27 (uint64 key, uint32 index) pairs: 2^10 distinct values, Zipf(1.1)
   and all-equal keys, with the default plan;
 * 2^20 uniform uint64 keys with one level, k = 256, b = 1, a = 16 and
-  base-case cutoff 1024.
+  base-case cutoff 1024;
+* the batch of 2227 log-uniform segments (2^28 keys in all), with the
+  built-in and with the autotuned parameters, every segment against the
+  oracle's sort of that segment.
 Inputs come from the same seeded generators and parameters as bench.py.
 """
 
 import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -160,3 +164,39 @@ def test_rlm_2p24_skewed_matches_oracle(api, dist):
     log("rlm %s 2^24+ on the GPU" % dist)
     got = host(api.rlm_sort_keys(to_dev(keys)))
     assert_same_bits(got, want, "rlm " + dist)
+
+
+def test_bench_batch_2p28(api):
+    import torch
+    # the batch workload exactly as bench.py draws it: 20,000 log-uniform
+    # sizes, the leading ones up to 2^28 keys in all, then the keys
+    rng = W.rng_for(bench.SPECIAL["batch_2^28"])
+    sizes = W.truncate_total(W.batch_sizes(20000, rng, 8, 20), 1 << 28)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    total = int(offs[-1])
+    keys = W.uniform_u64(total, rng)
+    assert sizes.size == 2227 and total > (1 << 28) - (1 << 20)
+    log("batch_2^28: oracle over %d segments on %d threads" % (sizes.size, threads()))
+    want = np.empty_like(keys)
+
+    def one(i):
+        a, b = int(offs[i]), int(offs[i + 1])
+        want[a:b] = oracle.oracle_sort(W.KEY_U64, keys[a:b])[0]
+
+    with ThreadPoolExecutor(threads()) as ex:
+        list(ex.map(one, range(sizes.size)))
+    d_keys = to_dev(keys)
+    d_offs = torch.from_numpy(offs.astype(np.int64)).cuda()
+    try:
+        tuned, _ = api.autotune(d_keys, offs, max_trials=16)
+        for label, params in (("built-in", None), ("autotuned", tuned)):
+            log("batch_2^28 on the GPU, %s parameters" % label)
+            ws = api.alloc_workspace(api.batch_workspace_bytes(W.KEY_U64, offs, params=params))
+            out = api.sort_batch(d_keys, offs, d_offsets=d_offs, params=params, workspace=ws)
+            st = api.workspace_stats(ws)
+            got = host(out)
+            del out, ws
+            assert st["device_errors"] == 0
+            assert_same_bits(got, want, "batch_2^28 " + label)
+    finally:
+        api.autotune_clear()  # later tests of this process use the built-in choice
