@@ -8,9 +8,9 @@ element against the oracle (its parallel mergesort on the host's cores).
   and all-equal keys, with the default plan;
 * 2^20 uniform uint64 keys with one level, k = 256, b = 1, a = 16 and
   base-case cutoff 1024;
-* the batch of 2227 log-uniform segments (2^28 keys in all), with the
-  built-in and with the autotuned parameters, every segment against the
-  oracle's sort of that segment.
+* the batches of 2227 and of 20,000 log-uniform segments (2^28 and about
+  2^31.2 keys in all), with the built-in and with the autotuned
+  parameters, every segment against the oracle's sort of that segment.
 Inputs come from the same seeded generators and parameters as bench.py.
 """
 
@@ -200,3 +200,49 @@ def test_bench_batch_2p28(api):
             assert_same_bits(got, want, "batch_2^28 " + label)
     finally:
         api.autotune_clear()  # later tests of this process use the built-in choice
+
+
+def test_bench_batch_20000(api):
+    import psutil
+    import torch
+    # configuration 4 as stated: 20,000 log-uniform segments, about 2^31.2
+    # keys (20 GB); the host holds the keys and the sorted output, and the
+    # oracle sorts one segment at a time beside the comparison
+    if psutil.virtual_memory().available < (64 << 30):
+        pytest.skip("needs about 48 GB of free host memory")
+    rng = W.rng_for(bench.SPECIAL["batch_20000"])
+    sizes = W.batch_sizes(20000, rng, 8, 20)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    total = int(offs[-1])
+    log("batch_20000: %d keys; generating" % total)
+    keys = W.uniform_u64(total, rng)
+    d_keys = to_dev(keys)
+    d_offs = torch.from_numpy(offs.astype(np.int64)).cuda()
+    bad = []
+
+    def check(got, label):
+        def one(i):
+            a, b = int(offs[i]), int(offs[i + 1])
+            want = oracle.oracle_sort(W.KEY_U64, keys[a:b])[0]
+            if not np.array_equal(got[a:b], want):
+                bad.append((label, i))
+
+        with ThreadPoolExecutor(threads()) as ex:
+            list(ex.map(one, range(sizes.size)))
+
+    try:
+        tuned, _ = api.autotune(d_keys, offs, max_trials=16)
+        for label, params in (("built-in", None), ("autotuned", tuned)):
+            log("batch_20000 on the GPU, %s parameters" % label)
+            ws = api.alloc_workspace(api.batch_workspace_bytes(W.KEY_U64, offs, params=params))
+            out = api.sort_batch(d_keys, offs, d_offsets=d_offs, params=params, workspace=ws)
+            st = api.workspace_stats(ws)
+            got = host(out)
+            del out, ws
+            assert st["device_errors"] == 0
+            log("batch_20000: oracle over %d segments on %d threads" % (sizes.size, threads()))
+            check(got, label)
+            del got
+            assert not bad, bad[:10]
+    finally:
+        api.autotune_clear()
