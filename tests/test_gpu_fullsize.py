@@ -10,7 +10,10 @@ element against the oracle (its parallel mergesort on the host's cores).
   base-case cutoff 1024;
 * the batches of 2227 and of 20,000 log-uniform segments (2^28 and about
   2^31.2 keys in all), with the built-in and with the autotuned
-  parameters, every segment against the oracle's sort of that segment.
+  parameters, every segment against the oracle's sort of that segment;
+* the serving workload's 1000 requests (mixed uint64, uint32 and float32
+  keys, 1.79e9 in all) queued at once into the server, every result
+  against the oracle's sort of its request.
 Inputs come from the same seeded generators and parameters as bench.py.
 """
 
@@ -246,3 +249,34 @@ def test_bench_batch_20000(api):
             assert not bad, bad[:10]
     finally:
         api.autotune_clear()
+
+
+def test_bench_serving_requests(api):
+    from paper_1410_6754_amd.server import Server
+    # the serving workload's requests exactly as bench.py draws them, all
+    # queued at once (its closed-loop pass); each result against the oracle
+    rng = W.rng_for(bench.SPECIAL["serving"])
+    nreq = 1000
+    _, sizes, kts = W.serving_stream(nreq, rng, 1.0, 10, 24)
+    log("serving: %d requests, %d keys; generating" % (nreq, int(sizes.sum())))
+    keys = [W.keys(int(kt), int(n), rng, "uniform") for n, kt in zip(sizes, kts)]
+    reqs = [to_dev(k) for k in keys]
+    bad = []
+
+    def check(i, got):
+        want = oracle.oracle_sort(int(kts[i]), keys[i])[0]
+        if not np.array_equal(got.view(np.uint8), want.view(np.uint8)):
+            bad.append(i)
+
+    with ThreadPoolExecutor(threads()) as ex, Server(streams=2, max_pending=nreq + 8) as srv:
+        tickets = [srv.submit(r) for r in reqs]
+        jobs = []
+        for i, tk in enumerate(tickets):
+            st = srv.wait(tk)
+            assert st["status"] == 0, (i, st)
+            got = host(srv.result(tk))
+            srv.release(tk)
+            jobs.append(ex.submit(check, i, got))
+        for j in jobs:
+            j.result()
+    assert not bad, bad[:10]
