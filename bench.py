@@ -461,9 +461,30 @@ def _log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def _flip64(t):
+def verify_batch_against_device_sort(d_keys, d_out, offs) -> bool:
+    """Every segment [offs[i], offs[i+1]) of d_out (uint64 keys) equals
+    torch's device sort of that segment of d_keys: a stable sort by key, then
+    a stable sort by segment, over runs of whole segments of at most 2^28
+    keys."""
     import torch
-    return t.view(torch.int64) ^ torch.iinfo(torch.int64).min
+    ok = True
+    num = len(offs) - 1
+    i = 0
+    while i < num:
+        j = i + 1
+        while j < num and int(offs[j + 1]) - int(offs[i]) <= (1 << 28):
+            j += 1
+        a, b = int(offs[i]), int(offs[j])
+        k = d_keys[a:b].view(torch.int64)
+        _, i1 = torch.sort(k ^ torch.iinfo(torch.int64).min, stable=True)
+        sz = torch.from_numpy((offs[i + 1:j + 1] - offs[i:j]).astype(np.int64)).to(k.device)
+        seg = torch.repeat_interleave(torch.arange(j - i, dtype=torch.int32, device=k.device), sz)
+        _, i2 = torch.sort(seg[i1], stable=True)
+        ok = ok and bool(torch.equal(k[i1[i2]], d_out[a:b].view(torch.int64)))
+        del i1, i2, seg, sz
+        i = j
+    torch.cuda.empty_cache()
+    return ok
 
 
 def _bits(t):
@@ -632,13 +653,10 @@ def bench_batch(args) -> int:
     ms_b, wall_b = time_batched(tuned)
     _log("batched, tuned parameters: %.3f ms per batch (wall %.3f ms)" % (ms_b, wall_b))
 
-    # verify: every segment sorted on the device, sampled segments equal numpy's sort
-    o = _flip64(d_out)
-    bad = o[1:] < o[:-1]
-    cut = torch.from_numpy(offs[1:-1].astype(np.int64) - 1).to(dev)
-    cut = cut[(cut >= 0) & (cut < bad.numel())]
-    bad[cut] = False
-    ok = not bool(bad.any().item())
+    # verify: every segment equals torch's device sort of it, and sampled
+    # segments equal numpy's sort
+    ok = verify_batch_against_device_sort(d_keys, d_out, offs)
+    _log("every segment equals the device reference sort: %s" % ok)
     for i in np.linspace(0, sizes.size - 1, 40).astype(int):
         a, b = int(offs[i]), int(offs[i + 1])
         ok = ok and np.array_equal(d_out[a:b].cpu().numpy(), np.sort(keys[a:b]))
