@@ -13,7 +13,10 @@ element against the oracle (its parallel mergesort on the host's cores).
   parameters, every segment against the oracle's sort of that segment;
 * the serving workload's 1000 requests (mixed uint64, uint32 and float32
   keys, 1.79e9 in all) queued at once into the server, every result
-  against the oracle's sort of its request.
+  against the oracle's sort of its request;
+* the largest accepted input, AMS_MAX_SEGMENT = 2^32 - 2^20 keys (uint32
+  and uint64): a permutation of 0..n-1, so the sorted output is known
+  without a host sort (the property holds at any size: output[j] = j).
 Inputs come from the same seeded generators and parameters as bench.py.
 """
 
@@ -280,3 +283,61 @@ def test_bench_serving_requests(api):
         for j in jobs:
             j.result()
     assert not bad, bad[:10]
+
+
+MAX_SEGMENT = (1 << 32) - (1 << 20)
+
+
+def _permutation_keys(n, wide):
+    """keys[i] = i * a mod n with gcd(a, n) = 1: a permutation of 0..n-1,
+    built on the device in chunks (64-bit products stay below 2^49)."""
+    import torch
+    a = 0x9E3779B1
+    ah, al = a >> 16, a & 0xFFFF
+    out = torch.empty(n, dtype=torch.int64 if wide else torch.int32, device="cuda")
+    step = 1 << 26
+    for s0 in range(0, n, step):
+        i = torch.arange(s0, min(s0 + step, n), dtype=torch.int64, device="cuda")
+        v = ((i * ah) % n * 65536 + i * al) % n
+        if not wide:
+            v = torch.where(v >= (1 << 31), v - (1 << 32), v).to(torch.int32)
+        out[s0:s0 + v.numel()] = v
+    return out.view(torch.uint64 if wide else torch.uint32)
+
+
+def _first_not_identity(out, n, wide):
+    import torch
+    step = 1 << 26
+    for s0 in range(0, n, step):
+        e = min(s0 + step, n)
+        g = out[s0:e].view(torch.int64 if wide else torch.int32).to(torch.int64)
+        if not wide:
+            g = g & 0xFFFFFFFF
+        want = torch.arange(s0, e, dtype=torch.int64, device=out.device)
+        if not torch.equal(g, want):
+            return s0 + int(torch.nonzero(g != want)[0])
+    return None
+
+
+@pytest.mark.parametrize("kt", [W.KEY_U32, W.KEY_U64])
+def test_max_segment(api, kt):
+    import torch
+    n = MAX_SEGMENT
+    wide = kt == W.KEY_U64
+    assert api.workspace_bytes(kt, n + 1, False, None) == 0  # one more is refused
+    log("max segment: %d %s keys; building the permutation" % (n, "uint64" if wide else "uint32"))
+    keys = _permutation_keys(n, wide)
+    probe = keys[:4].view(torch.int64 if wide else torch.int32).cpu().tolist()
+    assert probe[0] == 0 and probe[1] != 1  # i * a mod n, not the identity
+    ws = api.alloc_workspace(api.workspace_bytes(kt, n, False, None))
+    log("max segment: sorting")
+    out = api.sort_keys(keys, workspace=ws)
+    st = api.workspace_stats(ws)
+    log("max segment: levels %d, leaves %d, device errors %d"
+        % (st["levels"], st["leaves"], st["device_errors"]))
+    assert st["device_errors"] == 0
+    del keys, ws
+    bad = _first_not_identity(out, n, wide)
+    assert bad is None, "output[%d] != %d" % (bad, bad)
+    del out
+    torch.cuda.empty_cache()
