@@ -15,8 +15,9 @@ element against the oracle (its parallel mergesort on the host's cores).
   keys, 1.79e9 in all) queued at once into the server, every result
   against the oracle's sort of its request;
 * the largest accepted input, AMS_MAX_SEGMENT = 2^32 - 2^20 keys (uint32
-  and uint64): a permutation of 0..n-1, so the sorted output is known
-  without a host sort (the property holds at any size: output[j] = j).
+  and uint64 keys, uint32 pairs, RLM-sort): a permutation of 0..n-1, so the
+  sorted output is known without a host sort (the property holds at any
+  size: output[j] = j, and the payload of key j is its input position).
 Inputs come from the same seeded generators and parameters as bench.py.
 """
 
@@ -286,23 +287,28 @@ def test_bench_serving_requests(api):
 
 
 MAX_SEGMENT = (1 << 32) - (1 << 20)
+PERM_A = 0x9E3779B1  # coprime to MAX_SEGMENT = 2^20 * 3^2 * 5 * 7 * 13
 
 
 def _permutation_keys(n, wide):
     """keys[i] = i * a mod n with gcd(a, n) = 1: a permutation of 0..n-1,
     built on the device in chunks (64-bit products stay below 2^49)."""
     import torch
-    a = 0x9E3779B1
-    ah, al = a >> 16, a & 0xFFFF
+    a = PERM_A
     out = torch.empty(n, dtype=torch.int64 if wide else torch.int32, device="cuda")
     step = 1 << 26
     for s0 in range(0, n, step):
         i = torch.arange(s0, min(s0 + step, n), dtype=torch.int64, device="cuda")
-        v = ((i * ah) % n * 65536 + i * al) % n
+        v = _mulmod(i, a, n)
         if not wide:
             v = torch.where(v >= (1 << 31), v - (1 << 32), v).to(torch.int32)
         out[s0:s0 + v.numel()] = v
     return out.view(torch.uint64 if wide else torch.uint32)
+
+
+def _mulmod(i, a, n):
+    """i * a mod n for int64 tensors i < 2^32 and a < 2^32 (no product above 2^49)."""
+    return ((i * (a >> 16)) % n * 65536 + i * (a & 0xFFFF)) % n
 
 
 def _first_not_identity(out, n, wide):
@@ -336,6 +342,55 @@ def test_max_segment(api, kt):
     log("max segment: levels %d, leaves %d, device errors %d"
         % (st["levels"], st["leaves"], st["device_errors"]))
     assert st["device_errors"] == 0
+    del keys, ws
+    bad = _first_not_identity(out, n, wide)
+    assert bad is None, "output[%d] != %d" % (bad, bad)
+    del out
+    torch.cuda.empty_cache()
+
+
+def test_max_segment_pairs(api):
+    import torch
+    n = MAX_SEGMENT
+    log("max segment: %d uint32 pairs; building the permutation" % n)
+    keys = _permutation_keys(n, False)
+    vals = torch.empty(n, dtype=torch.int32, device="cuda")
+    step = 1 << 26
+    for s0 in range(0, n, step):
+        v = torch.arange(s0, min(s0 + step, n), dtype=torch.int64, device="cuda")
+        vals[s0:s0 + v.numel()] = torch.where(v >= (1 << 31), v - (1 << 32), v).to(torch.int32)
+    vals = vals.view(torch.uint32)
+    ws = api.alloc_workspace(api.workspace_bytes(W.KEY_U32, n, True, None))
+    log("max segment pairs: sorting")
+    ok, ov = api.sort_pairs(keys, vals, workspace=ws)
+    st = api.workspace_stats(ws)
+    assert st["device_errors"] == 0
+    del keys, vals, ws
+    bad = _first_not_identity(ok, n, False)
+    assert bad is None, "keys: output[%d] != %d" % (bad, bad)
+    # key j came from input position j * a^-1 mod n
+    ainv = pow(PERM_A, -1, n)
+    for s0 in range(0, n, step):
+        e = min(s0 + step, n)
+        j = torch.arange(s0, e, dtype=torch.int64, device="cuda")
+        g = ov[s0:e].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        assert torch.equal(g, _mulmod(j, ainv, n)), "payload in [%d, %d)" % (s0, e)
+    del ok, ov
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kt", [W.KEY_U32, W.KEY_U64])
+def test_max_segment_rlm(api, kt):
+    import torch
+    n = MAX_SEGMENT
+    wide = kt == W.KEY_U64
+    assert api.rlm_workspace_bytes(kt, n + 1) == 0
+    log("max segment RLM-sort: %d %s keys" % (n, "uint64" if wide else "uint32"))
+    keys = _permutation_keys(n, wide)
+    ws = api.alloc_workspace(api.rlm_workspace_bytes(kt, n))
+    out = api.rlm_sort_keys(keys, workspace=ws)
+    torch.cuda.synchronize()
+    assert api.device_errors() == 0
     del keys, ws
     bad = _first_not_identity(out, n, wide)
     assert bad is None, "output[%d] != %d" % (bad, bad)
