@@ -15,9 +15,11 @@ element against the oracle (its parallel mergesort on the host's cores).
   keys, 1.79e9 in all) queued at once into the server, every result
   against the oracle's sort of its request;
 * the largest accepted input, AMS_MAX_SEGMENT = 2^32 - 2^20 keys (uint32
-  and uint64 keys, uint32 pairs, RLM-sort): a permutation of 0..n-1, so the
-  sorted output is known without a host sort (the property holds at any
-  size: output[j] = j, and the payload of key j is its input position).
+  and uint64 keys, uint32 pairs, RLM-sort), and a batch of 5.4e9 keys whose
+  first segment has that size: each segment a permutation of 0..n-1, so
+  the sorted output is known without a host sort (the property holds at
+  any size: output[j] = j, and the payload of key j is its input
+  position).
 Inputs come from the same seeded generators and parameters as bench.py.
 """
 
@@ -290,19 +292,23 @@ MAX_SEGMENT = (1 << 32) - (1 << 20)
 PERM_A = 0x9E3779B1  # coprime to MAX_SEGMENT = 2^20 * 3^2 * 5 * 7 * 13
 
 
-def _permutation_keys(n, wide):
-    """keys[i] = i * a mod n with gcd(a, n) = 1: a permutation of 0..n-1,
-    built on the device in chunks (64-bit products stay below 2^49)."""
+def _fill_permutation(out, n, a, wide):
+    """out[i] = i * a mod n with gcd(a, n) = 1 (out: an int32 or int64 view of
+    n keys): a permutation of 0..n-1, built on the device in chunks."""
     import torch
-    a = PERM_A
-    out = torch.empty(n, dtype=torch.int64 if wide else torch.int32, device="cuda")
     step = 1 << 26
     for s0 in range(0, n, step):
-        i = torch.arange(s0, min(s0 + step, n), dtype=torch.int64, device="cuda")
+        i = torch.arange(s0, min(s0 + step, n), dtype=torch.int64, device=out.device)
         v = _mulmod(i, a, n)
         if not wide:
             v = torch.where(v >= (1 << 31), v - (1 << 32), v).to(torch.int32)
         out[s0:s0 + v.numel()] = v
+
+
+def _permutation_keys(n, wide):
+    import torch
+    out = torch.empty(n, dtype=torch.int64 if wide else torch.int32, device="cuda")
+    _fill_permutation(out, n, PERM_A, wide)
     return out.view(torch.uint64 if wide else torch.uint32)
 
 
@@ -394,5 +400,36 @@ def test_max_segment_rlm(api, kt):
     del keys, ws
     bad = _first_not_identity(out, n, wide)
     assert bad is None, "output[%d] != %d" % (bad, bad)
+    del out
+    torch.cuda.empty_cache()
+
+
+def test_batch_above_2p32_keys(api):
+    import math
+    import torch
+    # segment sizes: the largest accepted one first, so every later segment
+    # starts above 2^32 keys into the batch
+    sizes = [MAX_SEGMENT, (1 << 30) + 7, 3, 0, 1, (1 << 20) + 1, 4097]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    total = int(offs[-1])
+    assert total > (1 << 32) + (1 << 30)
+    log("batch of %d uint32 keys in %d segments; building the permutations" % (total, len(sizes)))
+    keys = torch.empty(total, dtype=torch.int32, device="cuda")
+    for i, n in enumerate(sizes):
+        if n:
+            a = PERM_A
+            while math.gcd(a, n) != 1:
+                a += 2
+            _fill_permutation(keys[int(offs[i]):int(offs[i + 1])], n, a, False)
+    keys = keys.view(torch.uint32)
+    ws = api.alloc_workspace(api.batch_workspace_bytes(W.KEY_U32, offs))
+    log("batch above 2^32 keys: sorting")
+    out = api.sort_batch(keys, offs, workspace=ws)
+    st = api.workspace_stats(ws)
+    assert st["device_errors"] == 0
+    del keys, ws
+    for i, n in enumerate(sizes):
+        bad = _first_not_identity(out[int(offs[i]):int(offs[i + 1])], n, False)
+        assert bad is None, "segment %d: output[%d] != %d" % (i, bad, bad)
     del out
     torch.cuda.empty_cache()
