@@ -15,7 +15,8 @@ element against the oracle (its parallel mergesort on the host's cores).
   keys, 1.79e9 in all) queued at once into the server, every result
   against the oracle's sort of its request;
 * the largest accepted input, AMS_MAX_SEGMENT = 2^32 - 2^20 keys (uint32
-  and uint64 keys, uint32 pairs, RLM-sort), and a batch of 5.4e9 keys whose
+  and uint64 keys, the same patterns as float32 under totalOrder, uint32
+  pairs, RLM-sort), and a batch of 5.4e9 keys whose
   first segment has that size: each segment a permutation of 0..n-1, so
   the sorted output is known without a host sort (the property holds at
   any size: output[j] = j, and the payload of key j is its input
@@ -329,6 +330,32 @@ def _first_not_identity(out, n, wide):
         if not torch.equal(g, want):
             return s0 + int(torch.nonzero(g != want)[0])
     return None
+
+
+def test_max_segment_float_bits(api):
+    import torch
+    # the same permutation of 0..n-1 read as float32 bit patterns: every
+    # positive pattern (+0 .. +NaN) and the negative ones from 0x80000000 (-0)
+    # to 0xFFEFFFFF (a negative NaN).  IEEE 754 totalOrder puts the negative
+    # patterns first, the largest pattern first, then the positive ones.
+    n = MAX_SEGMENT
+    log("max segment: %d float32 bit patterns; building the permutation" % n)
+    keys = _permutation_keys(n, False).view(torch.float32)
+    ws = api.alloc_workspace(api.workspace_bytes(W.KEY_F32, n, False, None))
+    out = api.sort_keys(keys, workspace=ws)
+    st = api.workspace_stats(ws)
+    assert st["device_errors"] == 0
+    del keys, ws
+    neg = n - (1 << 31)  # patterns 0x80000000 .. n-1
+    step = 1 << 26
+    for s0 in range(0, n, step):
+        e = min(s0 + step, n)
+        j = torch.arange(s0, e, dtype=torch.int64, device="cuda")
+        want = torch.where(j < neg, (n - 1) - j, j - neg)
+        g = out[s0:e].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        assert torch.equal(g, want), "float bits in [%d, %d)" % (s0, e)
+    del out
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("kt", [W.KEY_U32, W.KEY_U64])
