@@ -332,7 +332,8 @@ def _first_not_identity(out, n, wide):
     return None
 
 
-def test_max_segment_float_bits(api):
+@pytest.mark.parametrize("inplace", [False, True])
+def test_max_segment_float_bits(api, inplace):
     import torch
     # the same permutation of 0..n-1 read as float32 bit patterns: every
     # positive pattern (+0 .. +NaN) and the negative ones from 0x80000000 (-0)
@@ -342,7 +343,7 @@ def test_max_segment_float_bits(api):
     log("max segment: %d float32 bit patterns; building the permutation" % n)
     keys = _permutation_keys(n, False).view(torch.float32)
     ws = api.alloc_workspace(api.workspace_bytes(W.KEY_F32, n, False, None))
-    out = api.sort_keys(keys, workspace=ws)
+    out = api.sort_keys(keys, out=keys if inplace else None, workspace=ws)
     st = api.workspace_stats(ws)
     assert st["device_errors"] == 0
     del keys, ws
@@ -358,8 +359,8 @@ def test_max_segment_float_bits(api):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("kt", [W.KEY_U32, W.KEY_U64])
-def test_max_segment(api, kt):
+@pytest.mark.parametrize("kt,inplace", [(W.KEY_U32, False), (W.KEY_U64, False), (W.KEY_U64, True)])
+def test_max_segment(api, kt, inplace):
     import torch
     n = MAX_SEGMENT
     wide = kt == W.KEY_U64
@@ -369,8 +370,8 @@ def test_max_segment(api, kt):
     probe = keys[:4].view(torch.int64 if wide else torch.int32).cpu().tolist()
     assert probe[0] == 0 and probe[1] != 1  # i * a mod n, not the identity
     ws = api.alloc_workspace(api.workspace_bytes(kt, n, False, None))
-    log("max segment: sorting")
-    out = api.sort_keys(keys, workspace=ws)
+    log("max segment: sorting%s" % (" in place" if inplace else ""))
+    out = api.sort_keys(keys, out=keys if inplace else None, workspace=ws)
     st = api.workspace_stats(ws)
     log("max segment: levels %d, leaves %d, device errors %d"
         % (st["levels"], st["leaves"], st["device_errors"]))
