@@ -241,3 +241,34 @@ def test_in_place_float_duplicates(api, dist):
     wk, wv = oracle.oracle_sort(F32, keys, vals)
     assert_same_bits(to_host(dk), wk, "in place f32 pairs " + dist)
     assert np.array_equal(to_host(dv), wv)
+
+
+def test_sorts_on_concurrent_streams(api):
+    """Sorts enqueued on two streams at once, each with its own workspace,
+    run side by side on the device and equal the oracle: no state is shared
+    between calls beyond the per-device error word."""
+    import torch
+
+    import oracle
+    from gpu_util import assert_same_bits
+    cases = [(U64, gen(U64, (1 << 22) + 3, "uniform", 901)),
+             (F32, gen(F32, (1 << 21) + 5, "few", 902)),
+             (U32, gen(U32, 300001, "zipf", 903)),
+             (U64, gen(U64, 70001, "sorted", 904))]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ins = [to_dev(k) for _, k in cases]
+    wss = [api.alloc_workspace(api.workspace_bytes(kt, k.size, False, None)) for kt, k in cases]
+    outs = [torch.empty_like(x) for x in ins]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+    log("four sorts on two streams, three rounds")
+    for _ in range(3):
+        for i, x in enumerate(ins):
+            s = streams[i % 2]
+            with torch.cuda.stream(s):
+                api.sort_keys(x, out=outs[i], workspace=wss[i], stream=s)
+    for s in streams:
+        torch.cuda.current_stream().wait_stream(s)
+    for (kt, k), o in zip(cases, outs):
+        want, _ = oracle.oracle_sort(kt, k)
+        assert_same_bits(to_host(o), want, "kt%d n%d" % (kt, k.size))
