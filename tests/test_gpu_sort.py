@@ -244,9 +244,10 @@ def test_in_place_float_duplicates(api, dist):
 
 
 def test_sorts_on_concurrent_streams(api):
-    """Sorts enqueued on two streams at once, each with its own workspace,
-    run side by side on the device and equal the oracle: no state is shared
-    between calls beyond the per-device error word."""
+    """Sorts enqueued on two streams at once (keys of three types, then an
+    RLM-sort beside a pairs sort), each with its own workspace, run side by
+    side on the device and equal the oracle: no state is shared between
+    calls beyond the per-device error word."""
     import torch
 
     import oracle
@@ -267,8 +268,29 @@ def test_sorts_on_concurrent_streams(api):
             s = streams[i % 2]
             with torch.cuda.stream(s):
                 api.sort_keys(x, out=outs[i], workspace=wss[i], stream=s)
+    # an RLM-sort and a pairs sort join them, one on each stream
+    rk = gen(U64, (1 << 20) + 7, "uniform", 905)
+    pk = gen(U32, 200003, "few", 906)
+    pv = np.arange(pk.size, dtype=np.uint32)
+    d_rk, d_pk, d_pv = to_dev(rk), to_dev(pk), to_dev(pv)
+    ws_r = api.alloc_workspace(api.rlm_workspace_bytes(U64, rk.size))
+    ws_p = api.alloc_workspace(api.workspace_bytes(U32, pk.size, True, None))
+    o_r = torch.empty_like(d_rk)
+    o_pk, o_pv = torch.empty_like(d_pk), torch.empty_like(d_pv)
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+    for _ in range(2):
+        with torch.cuda.stream(streams[0]):
+            api.rlm_sort_keys(d_rk, out=o_r, workspace=ws_r, stream=streams[0])
+        with torch.cuda.stream(streams[1]):
+            api.sort_pairs(d_pk, d_pv, out_keys=o_pk, out_vals=o_pv, workspace=ws_p,
+                           stream=streams[1])
     for s in streams:
         torch.cuda.current_stream().wait_stream(s)
     for (kt, k), o in zip(cases, outs):
         want, _ = oracle.oracle_sort(kt, k)
         assert_same_bits(to_host(o), want, "kt%d n%d" % (kt, k.size))
+    assert_same_bits(to_host(o_r), oracle.oracle_sort(U64, rk)[0], "rlm")
+    wk, wv = oracle.oracle_sort(U32, pk, pv)
+    assert_same_bits(to_host(o_pk), wk, "pairs keys")
+    assert_same_bits(to_host(o_pv), wv, "pairs payload")
